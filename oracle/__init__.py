@@ -1,0 +1,190 @@
+"""ctypes wrapper of the FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the CPU
+baseline of the benchmark may import this package; the product path may not.
+It shares no code with the HIP implementation: its only input contract is the
+plain :class:`synth.WcsParams` container.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+NEAREST, BILINEAR, BICUBIC = 0, 1, 2
+INTERP = {"nearest": 0, "nearest-neighbor": 0, "bilinear": 1, "bicubic": 2}
+
+
+class OrcWcs(C.Structure):
+    _fields_ = [("crpix", C.c_double * 2), ("crval", C.c_double * 2), ("cd", C.c_double * 4),
+                ("a_order", C.c_int32), ("b_order", C.c_int32), ("ap_order", C.c_int32),
+                ("bp_order", C.c_int32), ("a", C.c_void_p), ("b", C.c_void_p),
+                ("ap", C.c_void_p), ("bp", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.orc_pix2world.argtypes = [C.POINTER(OrcWcs), C.c_double, C.c_double, dp, dp]
+        L.orc_world2pix.argtypes = [C.POINTER(OrcWcs), C.c_double, C.c_double, dp, dp]
+        L.orc_world2pix.restype = C.c_int
+        L.orc_world2pix_exact.argtypes = [C.POINTER(OrcWcs), C.c_double, C.c_double, dp, dp]
+        L.orc_world2pix_exact.restype = C.c_int
+        L.orc_pix2world_n.argtypes = [C.POINTER(OrcWcs), C.c_void_p, C.c_int64, C.c_void_p]
+        L.orc_world2pix_n.argtypes = [C.POINTER(OrcWcs), C.c_void_p, C.c_int64, C.c_void_p,
+                                      C.c_void_p, C.c_int]
+        L.orc_reproject_rows.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
+                                         C.POINTER(OrcWcs), C.POINTER(OrcWcs), C.c_int64,
+                                         C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_int,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.orc_interp_at.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
+                                    C.c_int64, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]
+        L.orc_interp.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_double,
+                                 C.c_double, C.c_int, C.c_double, dp, dp, dp]
+        L.orc_n_params.argtypes = [C.POINTER(OrcWcs)]
+        L.orc_n_params.restype = C.c_int64
+        L.orc_grad.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.POINTER(OrcWcs),
+                               C.POINTER(OrcWcs), C.c_int64, C.c_int64, C.c_int, C.c_double,
+                               C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_sip_eval.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
+        L.orc_sip_eval.restype = C.c_double
+        L.orc_online_cores.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class _W:
+    """Keeps the ctypes struct and the coefficient buffers it points to alive."""
+
+    def __init__(self, w):
+        self.keep = []
+        s = OrcWcs()
+        s.crpix[:] = list(w.crpix)
+        s.crval[:] = list(w.crval)
+        s.cd[:] = list(np.asarray(w.cd, dtype=np.float64).ravel())
+        for name in ("a", "b", "ap", "bp"):
+            c = getattr(w, name)
+            if c is None:
+                setattr(s, name + "_order", 0)
+                setattr(s, name, None)
+            else:
+                c = np.ascontiguousarray(c, dtype=np.float64)
+                self.keep.append(c)
+                setattr(s, name + "_order", c.shape[0] - 1)
+                setattr(s, name, c.ctypes.data)
+        self.s = s
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def _interp_id(interp):
+    return INTERP[interp] if isinstance(interp, str) else int(interp)
+
+
+def pix2world(w, xy):
+    """xy: [n, 2] pixel coordinates -> [n, 2] (ra, dec) degrees."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    out = np.empty_like(xy)
+    W = _W(w)
+    lib().orc_pix2world_n(W.ref, xy.ctypes.data, xy.shape[0], out.ctypes.data)
+    return out
+
+
+def world2pix(w, radec, exact=False):
+    """[n, 2] (ra, dec) -> ([n, 2] pixel, [n] valid).  exact=True inverts A/B by
+    Newton iteration instead of using AP/BP."""
+    radec = np.ascontiguousarray(radec, dtype=np.float64).reshape(-1, 2)
+    out = np.empty_like(radec)
+    valid = np.empty(radec.shape[0], dtype=np.int32)
+    W = _W(w)
+    lib().orc_world2pix_n(W.ref, radec.ctypes.data, radec.shape[0], out.ctypes.data,
+                          valid.ctypes.data, 1 if exact else 0)
+    return out, valid.astype(bool)
+
+
+def sip_eval(c, u, v):
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    return lib().orc_sip_eval(c.ctypes.data, c.shape[0] - 1, float(u), float(v))
+
+
+def reproject(src, src_wcs, tgt_wcs, out_shape=None, interp="bilinear", cubic_a=-0.5,
+              rows=None, threads=0, nan_outside=False, want_pos=False):
+    """FP64 reprojection of the target rows ``rows`` (default: all).
+
+    Returns (out, fp[, pos]) as float64 arrays of shape [len(rows), W_out]
+    (pos: [len(rows), W_out, 2])."""
+    src = np.ascontiguousarray(src, dtype=np.float32)
+    h, w = src.shape
+    if out_shape is None:
+        out_shape = (h, w)
+    oh, ow = out_shape
+    rows = np.arange(oh, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    n = rows.shape[0]
+    out = np.empty((n, ow), dtype=np.float64)
+    fp = np.empty((n, ow), dtype=np.float64)
+    pos = np.empty((n, ow, 2), dtype=np.float64) if want_pos else None
+    S, T = _W(src_wcs), _W(tgt_wcs)
+    lib().orc_reproject_rows(src.ctypes.data, h, w, w, S.ref, T.ref, ow, rows.ctypes.data, n,
+                             _interp_id(interp), float(cubic_a), 1 if nan_outside else 0,
+                             out.ctypes.data, fp.ctypes.data,
+                             pos.ctypes.data if pos is not None else None, int(threads))
+    return (out, fp, pos) if want_pos else (out, fp)
+
+
+def interp_at(src, pos, interp="bilinear", cubic_a=-0.5):
+    """Interpolate ``src`` at source positions pos [n, 2].
+
+    Returns (out, fp, cond) with cond = sum|w*src| / F (the scale against
+    which a relative error of the normalised value is measured)."""
+    src = np.ascontiguousarray(src, dtype=np.float32)
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 2)
+    n = pos.shape[0]
+    out = np.empty(n)
+    fp = np.empty(n)
+    cond = np.empty(n)
+    h, w = src.shape
+    lib().orc_interp_at(src.ctypes.data, h, w, w, pos.ctypes.data, n, _interp_id(interp),
+                        float(cubic_a), out.ctypes.data, fp.ctypes.data, cond.ctypes.data)
+    return out, fp, cond
+
+
+def n_params(src_wcs) -> int:
+    return int(lib().orc_n_params(_W(src_wcs).ref))
+
+
+def grad(src, src_wcs, tgt_wcs, out_shape, interp, grad_out, cubic_a=-0.5, want_src=True):
+    """Gradient of a loss with dL/dout = grad_out [H_out, W_out].
+
+    Returns (grad_src [H, W] float64 or None, grad_params [n_params]) with the
+    parameter order crval(2), crpix(2), cd(4), ap[(o+1)^2], bp[(o+1)^2]."""
+    src = np.ascontiguousarray(src, dtype=np.float32)
+    g = np.ascontiguousarray(grad_out, dtype=np.float64)
+    h, w = src.shape
+    oh, ow = out_shape
+    assert g.shape == (oh, ow)
+    S, T = _W(src_wcs), _W(tgt_wcs)
+    gp = np.zeros(lib().orc_n_params(S.ref))
+    gs = np.zeros((h, w)) if want_src else None
+    lib().orc_grad(src.ctypes.data, h, w, w, S.ref, T.ref, oh, ow, _interp_id(interp),
+                   float(cubic_a), g.ctypes.data, gs.ctypes.data if gs is not None else None,
+                   gp.ctypes.data)
+    return gs, gp
+
+
+def online_cores() -> int:
+    return int(lib().orc_online_cores())
