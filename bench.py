@@ -1,0 +1,309 @@
+#!/usr/bin/env python3
+"""Benchmark of the reprojection hot path on one MI355X.
+
+Headline: output Mpix/s of the bilinear forward reprojection of the
+6000x4000 frame with SIP A/B order 3 and fitted inverse AP/BP order 4
+(target 6000x4000 TAN, 40 px offset, rotated 0.3 deg), output and footprint
+float32, inputs resident in HBM.  One step = one full forward pass over the
+frame (host set-up + one kernel launch through the C ABI).
+
+Beside it: the roofline of that kernel (algorithmic bytes per launch over the
+launch's average duration from HIP events on its stream, against 8 TB/s),
+the FP64 CPU oracle timed on this host, and the other forms of the path
+(nearest and bicubic, the FP64 and trigonometric forms, forward+backward on
+the 2048^2 alignment case, the 64-frame batch, the +89.5 deg precision case).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2505_03932_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(name: str):
+    """HBM traffic of the headline kernel from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        for line in f:
+            if line.startswith("<!--traffic "):
+                d = json.loads(line[len("<!--traffic "):].rsplit("-->", 1)[0])
+                if d.get("kernel_source_hash") == kernel_source_hash():
+                    return d
+    return None
+
+
+class Frame:
+    """Device buffers and prebuilt C structs for repeated launches."""
+
+    def __init__(self, dfr, src_np, sw, tw, shape, interp, n_sets=2, precision="f32", fp=True):
+        import torch
+        from paper_2505_03932_amd import api
+        self.api = api
+        self.lib = api._lib
+        self.shape = shape
+        self.interp = api.ORDERS[interp]
+        self.sets = []
+        for _ in range(n_sets):
+            s = torch.from_numpy(src_np).cuda()
+            o = torch.empty(shape, dtype=torch.float32, device="cuda")
+            f = torch.empty(shape, dtype=torch.float32, device="cuda") if fp else None
+            self.sets.append((s, o, f))
+        self.sw = api.CWcs(sw)
+        self.tw = api.CWcs(tw)
+        self.opt = api._opts(precision)
+        self.stream = torch.cuda.current_stream().cuda_stream
+        self.k = 0
+
+    def step(self):
+        s, o, f = self.sets[self.k % len(self.sets)]
+        self.k += 1
+        st = self.lib.dfr_reproject(s.data_ptr(), s.shape[0], s.shape[1], s.stride(0), self.sw.s,
+                                    self.tw.s, self.shape[0], self.shape[1], self.interp,
+                                    o.data_ptr(), f.data_ptr() if f is not None else None,
+                                    self.opt, self.stream)
+        if st != 0:
+            raise RuntimeError(f"dfr_reproject failed: {st}")
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def touched_source_pixels(dfr, src_t, sw, tw, shape, interp):
+    """Distinct source pixels the interpolation reads: the support of the
+    adjoint applied to an all-ones output gradient."""
+    import torch
+    g = torch.ones(shape, dtype=torch.float32, device="cuda")
+    gs, _ = dfr.reproject_backward(src_t, sw, tw, shape, interp, g, want_wcs=False)
+    torch.cuda.synchronize()
+    return int(torch.count_nonzero(gs).item())
+
+
+def cpu_baseline(case, interp):
+    import oracle
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    rows = np.arange(0, case.out_shape[0], 2, dtype=np.int64)  # every other row
+    oracle.reproject(case.src, case.src_wcs, case.tgt_wcs, case.out_shape, interp,
+                     rows=rows[:8], threads=threads)
+    t0 = time.perf_counter()
+    oracle.reproject(case.src, case.src_wcs, case.tgt_wcs, case.out_shape, interp, rows=rows,
+                     threads=threads)
+    dt = time.perf_counter() - t0
+    npx = rows.size * case.out_shape[1]
+    return {"value": round(npx / dt / 1e6, 3), "unit": "Mpix/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"every other output row of the 6000x4000 SIP frame ({npx} px, "
+                      f"{interp}), FP64, {dt:.1f} s wall"}
+
+
+# ------------------------------------------------------------------ extras --
+
+def extra_forms(dfr, case, steps):
+    """Nearest/bicubic and the FP64 forms on the same frame."""
+    res = {}
+    npx = case.out_shape[0] * case.out_shape[1]
+    for interp in ("nearest", "bicubic"):
+        fr = Frame(dfr, case.src, case.src_wcs, case.tgt_wcs, case.out_shape, interp)
+        ms, _ = time_steps(fr.step, steps, 2)
+        res[f"sip3_{interp}"] = {"mpix_s": round(npx / ms / 1e3, 1), "ms": round(ms, 4)}
+        del fr
+    for prec in ("f64", "trig"):
+        fr = Frame(dfr, case.src, case.src_wcs, case.tgt_wcs, case.out_shape, "bilinear",
+                   precision=prec, n_sets=1)
+        ms, _ = time_steps(fr.step, max(2, steps // 4), 1)
+        res[f"sip3_bilinear_{prec}"] = {"mpix_s": round(npx / ms / 1e3, 1), "ms": round(ms, 4)}
+        del fr
+    return res
+
+
+def extra_grad(dfr, steps):
+    """Forward + loss + backward on the 2048^2 bicubic alignment case."""
+    import torch
+    from synth import configs
+    c = configs.grad()
+    src = torch.from_numpy(c.src).cuda()
+    true_w = c.extra["src_wcs_true"]
+    ref, _ = dfr.reproject(src, true_w, c.tgt_wcs, c.out_shape, "bicubic")
+    n = c.out_shape[0] * c.out_shape[1]
+
+    def fwd():
+        out, _ = dfr.reproject(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic", footprint=False)
+        return out
+
+    def step():
+        out = fwd()
+        loss, g = dfr.sq_residual(out, ref)
+        dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic", g)
+
+    ms_f, _ = time_steps(fwd, steps, 2)
+    ms_fb, _ = time_steps(step, steps, 2)
+    return {"grad2048_bicubic_fwd": {"mpix_s": round(n / ms_f / 1e3, 1), "ms": round(ms_f, 4)},
+            "grad2048_bicubic_fwd_bwd": {"mpix_s": round(n / ms_fb / 1e3, 1),
+                                         "ms": round(ms_fb, 4)}}
+
+
+def extra_batch(dfr, steps):
+    """64 uneven frames onto one 8192^2 grid in one graph-replayed launch."""
+    import torch
+    from synth import configs
+    t0 = time.perf_counter()
+    c = configs.batch()
+    log(f"batch inputs generated in {time.perf_counter() - t0:.1f} s")
+    srcs = [torch.from_numpy(s).cuda() for s in c.src]
+    oh, ow = c.out_shape
+    outs = [torch.empty((oh, ow), dtype=torch.float32, device="cuda") for _ in srcs]
+    fps = [torch.empty((oh, ow), dtype=torch.float32, device="cuda") for _ in srcs]
+    tile = dfr.api.reproject_batch(srcs, c.src_wcs, c.tgt_wcs, c.out_shape, "bilinear",
+                                   outs=outs, fps=fps, autotune=True)
+    ms, _ = time_steps(lambda: dfr.reproject_batch(srcs, c.src_wcs, c.tgt_wcs, c.out_shape,
+                                                   "bilinear", outs=outs, fps=fps),
+                       max(2, steps // 4), 1)
+    npx = len(srcs) * oh * ow
+    src_bytes = sum(s.numel() * 4 for s in srcs)
+    byts = npx * 8 + src_bytes
+    res = {"batch64_8192_bilinear": {"mpix_s": round(npx / ms / 1e3, 1), "ms": round(ms, 3),
+                                     "gbs_alg": round(byts / ms / 1e6, 1),
+                                     "hbm_frac": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)}}
+    del outs, fps, srcs
+    torch.cuda.empty_cache()
+    return res
+
+
+def extra_pole(dfr, steps):
+    """+89.5 deg, 0.2"/px, 8192^2, rotated 45 deg, SIP 4: FP32 vs FP64 path."""
+    import torch
+    from synth import configs
+    c = configs.pole()
+    src = torch.from_numpy(c.src).cuda()
+    npx = c.out_shape[0] * c.out_shape[1]
+    res = {}
+    pos = {}
+    for prec in ("f32", "f64"):
+        _, _, p = dfr.reproject(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bilinear",
+                                precision=prec, debug_positions=True)
+        pos[prec] = p
+        fr = Frame(dfr, c.src, c.src_wcs, c.tgt_wcs, c.out_shape, "bilinear", precision=prec,
+                   n_sets=1)
+        ms, _ = time_steps(fr.step, max(2, steps // 4), 1)
+        res[f"pole8192_bilinear_{prec}"] = {"mpix_s": round(npx / ms / 1e3, 1), "ms": round(ms, 3)}
+        del fr
+    ok = torch.isfinite(pos["f32"][..., 0]) & torch.isfinite(pos["f64"][..., 0])
+    d = torch.linalg.norm(pos["f32"][ok] - pos["f64"][ok], dim=-1)
+    res["pole8192_fp32_vs_fp64_pos_err_px"] = {"max": float(d.max()), "rms": float(
+        torch.sqrt(torch.mean(d * d)))}
+    del pos, src
+    torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build runs the reprojection on a single MI355X "
+              "(no multi-GPU path); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2505_03932_amd as dfr
+    from synth import configs
+
+    t0 = time.perf_counter()
+    case = configs.sip3(interp=1)
+    log(f"sip3 inputs generated in {time.perf_counter() - t0:.1f} s")
+    oh, ow = case.out_shape
+    npx = oh * ow
+    frame = Frame(dfr, case.src, case.src_wcs, case.tgt_wcs, case.out_shape, "bilinear")
+    ms, wall = time_steps(frame.step, args.steps, args.warmup)
+    value = npx / ms / 1e3  # Mpix/s
+    src_t = frame.sets[0][0]
+    touched = touched_source_pixels(dfr, src_t, case.src_wcs, case.tgt_wcs, case.out_shape,
+                                    "bilinear")
+    alg_bytes = 8 * npx + 4 * touched
+    achieved = alg_bytes / ms / 1e6  # GB/s
+    traffic = stored_traffic("reproject_sip3_bilinear_pmc.md")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": (traffic or {}).get("bytes_per_launch"),
+            "alg_bytes_per_launch": alg_bytes, "kernel_ms": round(ms, 5),
+            "touched_src_px": touched}
+    del frame
+    torch.cuda.empty_cache()
+
+    forms = {}
+    if not args.no_extras:
+        for fn in (lambda: extra_forms(dfr, case, args.steps), lambda: extra_grad(dfr, args.steps),
+                   lambda: extra_pole(dfr, args.steps), lambda: extra_batch(dfr, args.steps)):
+            try:
+                forms.update(fn())
+            except Exception as e:  # an extra must not hide the headline
+                forms.setdefault("errors", []).append(repr(e))
+            log("extras so far:", json.dumps(forms))
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(case, "bilinear")
+
+    line = {
+        "metric": "output Mpix/s (bilinear/bicubic, SIP-3) + % HBM roofline; fwd+bwd Mpix/s",
+        "value": round(value, 1), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded star field, SIP order 3 + fitted inverse order 4)",
+        "config": {"workload": "6000x4000 SIP-3 frame -> 6000x4000 TAN target, bilinear, "
+                               "out+footprint f32", "out_px": npx},
+        "roofline": roof, "cpu_baseline": cpu, "forms": forms,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

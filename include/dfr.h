@@ -1,0 +1,197 @@
+/*
+ * dfr — per-pixel astronomical image reprojection on AMD Instinct MI355X
+ * (gfx950).  C ABI of libdfr.so.
+ *
+ * The operation (paper "dfreproject: A Python package for astronomical
+ * reprojection", section 3): every output pixel is taken through the target
+ * WCS to the sky (shift, SIP A/B distortion, CD matrix, gnomonic
+ * deprojection and spherical rotation, section 3.2.1), then through the
+ * source WCS back to a source-pixel position (inverse rotation and gnomonic
+ * projection, inverse CD, inverse SIP AP/BP, shift, section 3.2.2); the
+ * source image is interpolated there (nearest, bilinear or bicubic,
+ * section 3.1 step 3) together with a footprint (the interpolation of a
+ * ones image), and the output is normalised by that footprint (section
+ * 3.1, last paragraph).  The calls mirror the paper's single-call API
+ * (source image + WCS, target WCS, output shape, interpolation order;
+ * section 2).
+ *
+ * Conventions used by every call
+ *   - x is the 0-based column (FITS NAXIS1, contiguous in memory), y the
+ *     0-based row; integer coordinates are pixel centres.  Images are
+ *     row-major float32, [rows][pitch] for sources and dense [out_h][out_w]
+ *     for outputs.
+ *   - CRPIX is FITS 1-based; CRVAL (RA, Dec) and CD are in degrees.
+ *   - SIP polynomials (Shupe et al. 2005) are added: u' = u + A(u, v),
+ *     v' = v + B(u, v), both evaluated at the undistorted (u, v); the
+ *     inverse likewise with AP/BP.  The longitude of the pole is 180 deg
+ *     (the TAN default that the paper's equations imply).
+ *   - Interpolation reads zero outside the source: the value S and the
+ *     footprint F sum only in-bounds taps.  Where F > 0 the output is S/F
+ *     and the footprint is F; elsewhere (including directions on or behind
+ *     the source tangent plane) the output is 0 (NaN with nan_outside) and
+ *     the footprint 0.  Nearest rounds half to even.  Bicubic is Keys cubic
+ *     convolution with parameter cubic_a (default -0.5).
+ *   - Image pointers are DEVICE memory owned by the caller; WCS structs,
+ *     coefficient arrays and option structs are HOST memory, read during
+ *     the call only.  Work is enqueued on `stream` (a hipStream_t; NULL is
+ *     the default stream) and is complete once that stream is synchronised.
+ *   - Argument errors are detected on the host before any device work is
+ *     enqueued; outputs are then left untouched.  On DFR_OK every output
+ *     pixel is written, so outputs need no clearing by the caller.
+ *   - The library keeps per-device workspaces (released by dfr_release) and
+ *     a tile-shape cache; calls may come from several host threads.
+ */
+#ifndef DFR_H
+#define DFR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DFR_MAX_SIP_ORDER 9
+#define DFR_ABI_VERSION 1
+
+typedef struct dfr_wcs {
+  double crpix[2];       /* CRPIX1, CRPIX2 (1-based)                              */
+  double crval[2];       /* CRVAL1 = RA, CRVAL2 = Dec, degrees; |Dec| <= 90       */
+  double cd[4];          /* CD1_1, CD1_2, CD2_1, CD2_2, degrees per pixel         */
+  int32_t a_order, b_order, ap_order, bp_order; /* 0 = polynomial absent       */
+  /* (order+1)^2 doubles each, element [p*(order+1)+q] = coefficient of
+   * u^p v^q; entries with p+q > order must be 0.  NULL when order is 0. */
+  const double *a, *b, *ap, *bp;
+} dfr_wcs;
+
+typedef enum { DFR_NEAREST = 0, DFR_BILINEAR = 1, DFR_BICUBIC = 2 } dfr_interp;
+
+typedef enum {
+  DFR_OK = 0,
+  DFR_E_NULL = 1,        /* a required pointer is NULL                              */
+  DFR_E_SHAPE = 2,       /* negative size, pitch < width, or size overflow           */
+  DFR_E_WCS = 3,         /* non-finite value, singular CD, |Dec| > 90, SIP term with
+                            p+q > order, or SIP order outside [0, DFR_MAX_SIP_ORDER] */
+  DFR_E_UNSUPPORTED = 4, /* unknown interpolation/precision, or a source WCS with
+                            forward SIP A/B but no inverse AP/BP                     */
+  DFR_E_DEVICE = 5,      /* a HIP runtime call or kernel launch failed               */
+  DFR_E_NOMEM = 6,       /* device or host allocation failed                          */
+  DFR_E_ARG = 7          /* other invalid argument (option struct size, count, ...)  */
+} dfr_status;
+
+typedef enum {
+  DFR_PREC_F32 = 0,      /* FP64 per-anchor set-up, FP32 per-pixel offsets (default) */
+  DFR_PREC_F64 = 1,      /* every pixel in FP64 through the composed rotation        */
+  DFR_PREC_TRIG_F64 = 2  /* every pixel in FP64 through explicit (RA, Dec) and the
+                            trigonometric two-stage form of section 3.2              */
+} dfr_precision;
+
+typedef struct dfr_options {
+  uint32_t size;          /* sizeof(dfr_options); checked for ABI compatibility    */
+  int32_t precision;      /* dfr_precision                                           */
+  double cubic_a;         /* Keys parameter for bicubic; -0.5 by default             */
+  int32_t nan_outside;    /* nonzero: uncovered output pixels are NaN, not 0          */
+  int32_t tile;           /* 0 = choose (tuned cache or heuristic); else a tile id    */
+  /* Nullable DEVICE buffer [out_h][out_w][2] of doubles: receives the source
+   * position each pixel was interpolated at (exactly the value the kernel
+   * used; NaN where the direction has no source position).  For tests.     */
+  double *debug_positions;
+} dfr_options;
+
+/* Fill `opt` with the defaults (FP32 path, a = -0.5, zeros outside, auto tile). */
+void dfr_options_init(dfr_options *opt);
+
+/* Reproject one source image onto the target grid (section 3; the paper's
+ * single-call API of section 2).
+ *   src        device, [src_h][src_pitch] float32 (may be NULL if src_h or
+ *              src_w is 0: then every output pixel is uncovered)
+ *   out        device, [out_h][out_w] float32 (may be NULL when out_h*out_w=0)
+ *   footprint  device, [out_h][out_w] float32, nullable
+ *   opt        host, nullable (defaults)                                      */
+dfr_status dfr_reproject(const float *src, int32_t src_h, int32_t src_w, int64_t src_pitch,
+                         const dfr_wcs *src_wcs, const dfr_wcs *tgt_wcs,
+                         int32_t out_h, int32_t out_w, dfr_interp interp,
+                         float *out, float *footprint, const dfr_options *opt,
+                         void *stream);
+
+/* One sub-exposure of a batch (the paper's use case: many exposures stacked
+ * onto one target grid, section 1). */
+typedef struct dfr_frame {
+  const float *src;       /* device, [h][pitch] float32                          */
+  int32_t h, w;
+  int64_t pitch;
+  dfr_wcs wcs;
+} dfr_frame;
+
+/* Reproject n frames of uneven sizes onto one target grid in a single
+ * persistent launch replayed from a captured HIP graph.  outs[i] and
+ * footprints[i] are device [out_h][out_w] float32 (footprints or any entry
+ * of it nullable).  The result of every frame is bit-identical to
+ * dfr_reproject of that frame with the same options.  The graph is cached
+ * per (n, out shape, interp, orders, tile) and replayed when they repeat. */
+dfr_status dfr_reproject_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_wcs,
+                               int32_t out_h, int32_t out_w, dfr_interp interp,
+                               float *const *outs, float *const *footprints,
+                               const dfr_options *opt, void *stream);
+
+/* Number of source-WCS gradient entries dfr_reproject_backward writes:
+ * crval(2), crpix(2), cd(4), ap[(ap_order+1)^2], bp[(bp_order+1)^2]. */
+int64_t dfr_wcs_grad_size(const dfr_wcs *src_wcs);
+
+/* Backward pass of dfr_reproject (FP32 path) for a loss L with
+ * grad_out = dL/dout ([out_h][out_w] float32, device):
+ *   grad_src  device [src_h][src_w] float32, nullable, overwritten:
+ *             dL/dsrc = adjoint of the interpolation (scatter-add of w*g/F);
+ *   grad_wcs  device float64 [dfr_wcs_grad_size(src_wcs)], nullable,
+ *             overwritten: dL/d(source CRVAL, CRPIX, CD, AP, BP) in degrees
+ *             and pixels; AP/BP entries with p+q > order are 0.
+ * Pixels with F <= 0 contribute nothing.  Nearest gives zero WCS gradient. */
+dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w,
+                                  int64_t src_pitch, const dfr_wcs *src_wcs,
+                                  const dfr_wcs *tgt_wcs, int32_t out_h, int32_t out_w,
+                                  dfr_interp interp, const float *grad_out, float *grad_src,
+                                  double *grad_wcs, const dfr_options *opt, void *stream);
+
+/* Squared-residual loss for WCS alignment: over n pixels,
+ *   loss = sum_i m_i (out_i - ref_i)^2  and  grad_out_i = 2 m_i (out_i - ref_i),
+ * with m_i = mask[i] (device float32, nullable = all ones).  loss is a device
+ * double (overwritten), grad_out device float32 [n] (nullable). */
+dfr_status dfr_sq_residual(const float *out, const float *ref, const float *mask, int64_t n,
+                           double *loss, float *grad_out, void *stream);
+
+/* Time the candidate tile shapes for this reprojection on `stream` (the
+ * outputs are written, with identical values, by every candidate), store the
+ * fastest in the tile cache (and in the JSON file named by the environment
+ * variable DFR_TUNE_CACHE, if set) and return its id in *tile.  Tile shape
+ * never changes results. */
+dfr_status dfr_autotune(const float *src, int32_t src_h, int32_t src_w, int64_t src_pitch,
+                        const dfr_wcs *src_wcs, const dfr_wcs *tgt_wcs, int32_t out_h,
+                        int32_t out_w, dfr_interp interp, float *out, float *footprint,
+                        const dfr_options *opt, void *stream, int32_t *tile);
+
+/* As dfr_autotune, for a batch (times whole persistent launches). */
+dfr_status dfr_autotune_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_wcs,
+                              int32_t out_h, int32_t out_w, dfr_interp interp,
+                              float *const *outs, float *const *footprints,
+                              const dfr_options *opt, void *stream, int32_t *tile);
+
+/* Number of tile shapes and the (width, height) in output pixels of tile
+ * id 1..dfr_tile_count(); returns DFR_E_ARG for an unknown id. */
+int32_t dfr_tile_count(void);
+dfr_status dfr_tile_shape(int32_t tile, int32_t *width, int32_t *height);
+
+/* CD matrix from PC and CDELT (section 3.1): CD_ij = CDELT_i * PC_ij. */
+void dfr_cd_from_pc_cdelt(const double pc[4], const double cdelt[2], double cd[4]);
+
+/* Validate a WCS the way every entry point does (host only, no device). */
+dfr_status dfr_check_wcs(const dfr_wcs *wcs, int32_t as_source);
+
+/* Free cached per-device workspaces and graphs (the calling thread's device). */
+dfr_status dfr_release(void);
+
+const char *dfr_strerror(dfr_status status);
+int32_t dfr_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,331 @@
+"""Torch-facing API over the C ABI (argument marshalling only).
+
+PyTorch provides device memory and streams; every step of the reprojection
+runs in libdfr's HIP kernels.
+
+  reproject(src, src_wcs, tgt_wcs, shape_out, order)       single image
+  calculate_reprojection(source_hdus, target_wcs, ...)     the paper's call
+  reproject_batch(srcs, src_wcss, tgt_wcs, shape_out)      many frames
+  ReprojectFn / reproject_differentiable(...)              autograd
+  sq_residual(out, ref, mask)                              alignment loss
+
+A WCS is any object with ``crpix``, ``crval``, ``cd`` (2x2) and optional SIP
+arrays ``a``, ``b``, ``ap``, ``bp`` ((order+1, order+1), [p, q] = coefficient
+of u**p v**q), or a FITS-style header mapping (see :func:`wcs_from_header`).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import DfrError
+
+ORDERS = {"nearest": 0, "nearest-neighbor": 0, "nearest_neighbor": 0, "bilinear": 1,
+          "bicubic": 2, 0: 0, 1: 1, 2: 2}
+PRECISIONS = {"f32": 0, "fp32": 0, "f64": 1, "fp64": 1, "trig": 2, "trig_f64": 2, 0: 0, 1: 1, 2: 2}
+
+
+@dataclass
+class Wcs:
+    """TAN (+SIP) world coordinate system (FITS conventions, degrees)."""
+
+    crpix: tuple
+    crval: tuple
+    cd: np.ndarray
+    a: Optional[np.ndarray] = None
+    b: Optional[np.ndarray] = None
+    ap: Optional[np.ndarray] = None
+    bp: Optional[np.ndarray] = None
+
+
+def _sip_from_header(h, name):
+    order = int(h.get(f"{name}_ORDER", 0))
+    if order <= 0:
+        return None
+    c = np.zeros((order + 1, order + 1))
+    for p in range(order + 1):
+        for q in range(order + 1 - p):
+            c[p, q] = float(h.get(f"{name}_{p}_{q}", 0.0))
+    return c
+
+
+def wcs_from_header(h) -> Wcs:
+    """WCS from a FITS-style header mapping (CRPIXi, CRVALi, CDi_j or
+    PCi_j x CDELTi (paper section 3.1), A/B/AP/BP_ORDER and A_p_q ...)."""
+    crpix = (float(h["CRPIX1"]), float(h["CRPIX2"]))
+    crval = (float(h["CRVAL1"]), float(h["CRVAL2"]))
+    if "CD1_1" in h:
+        cd = [float(h.get(k, 0.0)) for k in ("CD1_1", "CD1_2", "CD2_1", "CD2_2")]
+    else:
+        pc = [float(h.get(k, 1.0 if k in ("PC1_1", "PC2_2") else 0.0))
+              for k in ("PC1_1", "PC1_2", "PC2_1", "PC2_2")]
+        cdelt = [float(h.get("CDELT1", 1.0)), float(h.get("CDELT2", 1.0))]
+        cd = _lib.dfr_cd_from_pc_cdelt(pc, cdelt)
+    return Wcs(crpix, crval, np.array(cd).reshape(2, 2), _sip_from_header(h, "A"),
+               _sip_from_header(h, "B"), _sip_from_header(h, "AP"), _sip_from_header(h, "BP"))
+
+
+def as_wcs(w):
+    if isinstance(w, dict) or (hasattr(w, "keys") and "CRPIX1" in w):
+        return wcs_from_header(w)
+    return w
+
+
+class CWcs:
+    """A dfr_wcs struct with the coefficient buffers it points to."""
+
+    def __init__(self, w):
+        w = as_wcs(w)
+        self.keep = []
+        s = _lib.dfr_wcs()
+        s.crpix[:] = [float(v) for v in w.crpix]
+        s.crval[:] = [float(v) for v in w.crval]
+        s.cd[:] = [float(v) for v in np.asarray(w.cd, dtype=np.float64).ravel()]
+        for name in ("a", "b", "ap", "bp"):
+            c = getattr(w, name, None)
+            if c is None:
+                setattr(s, name + "_order", 0)
+                setattr(s, name, None)
+            else:
+                c = np.ascontiguousarray(c, dtype=np.float64)
+                self.keep.append(c)
+                setattr(s, name + "_order", c.shape[0] - 1)
+                setattr(s, name, c.ctypes.data)
+        self.s = s
+
+
+def _opts(precision="f32", cubic_a=-0.5, nan_outside=False, tile=0, debug=None):
+    o = _lib.dfr_options()
+    _lib.dfr_options_init(o)
+    o.precision = PRECISIONS[precision]
+    o.cubic_a = float(cubic_a)
+    o.nan_outside = 1 if nan_outside else 0
+    o.tile = int(tile)
+    o.debug_positions = debug
+    return o
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _check(status: int, where: str):
+    if status != _lib.DFR_OK:
+        raise DfrError(status, where)
+
+
+def _src_tensor(src) -> torch.Tensor:
+    if not isinstance(src, torch.Tensor):
+        src = torch.as_tensor(np.ascontiguousarray(src, dtype=np.float32))
+    if not src.is_cuda:
+        src = src.cuda()
+    if src.dtype != torch.float32:
+        src = src.float()
+    if src.dim() != 2:
+        raise ValueError("source image must be 2-D [rows, cols]")
+    if src.stride(1) != 1:
+        src = src.contiguous()
+    return src
+
+
+def reproject(src, src_wcs, tgt_wcs, shape_out=None, order="bilinear", *, footprint=True,
+              out=None, fp=None, precision="f32", cubic_a=-0.5, nan_outside=False, tile=0,
+              debug_positions=False):
+    """Reproject one image.  Returns (out, footprint) float32 tensors on the
+    source's device (footprint None if footprint=False); with
+    debug_positions=True also the float64 [H, W, 2] source positions."""
+    src = _src_tensor(src)
+    if shape_out is None:
+        shape_out = tuple(src.shape)
+    oh, ow = int(shape_out[0]), int(shape_out[1])
+    dev = src.device
+    if out is None:
+        out = torch.empty((oh, ow), dtype=torch.float32, device=dev)
+    if footprint and fp is None:
+        fp = torch.empty((oh, ow), dtype=torch.float32, device=dev)
+    pos = torch.empty((oh, ow, 2), dtype=torch.float64, device=dev) if debug_positions else None
+    sw, tw = CWcs(src_wcs), CWcs(tgt_wcs)
+    o = _opts(precision, cubic_a, nan_outside, tile, _ptr(pos))
+    s = _lib.dfr_reproject(src.data_ptr(), src.shape[0], src.shape[1], src.stride(0), sw.s, tw.s,
+                           oh, ow, ORDERS[order], _ptr(out), _ptr(fp if footprint else None), o,
+                           _stream(dev))
+    _check(s, "dfr_reproject")
+    if debug_positions:
+        return out, (fp if footprint else None), pos
+    return out, (fp if footprint else None)
+
+
+def calculate_reprojection(source_hdus, target_wcs, shape_out=None, order="bilinear", *,
+                           return_footprint=False, device=None):
+    """The paper's single call (section 2): ``source_hdus`` is a (data, wcs)
+    pair (or an object with .data and .header); ``target_wcs`` a WCS or a
+    header mapping; ``shape_out`` defaults to the source shape."""
+    if hasattr(source_hdus, "data") and hasattr(source_hdus, "header"):
+        data, wcs = source_hdus.data, source_hdus.header
+    else:
+        data, wcs = source_hdus
+    src = torch.as_tensor(np.ascontiguousarray(data, dtype=np.float32)) \
+        if not isinstance(data, torch.Tensor) else data
+    src = src.to(device or ("cuda" if not src.is_cuda else src.device))
+    out, fp = reproject(src, wcs, target_wcs, shape_out, order)
+    return (out, fp) if return_footprint else out
+
+
+def _frames(srcs, wcss):
+    frames = (_lib.dfr_frame * len(srcs))()
+    keep = []
+    for i, (s, w) in enumerate(zip(srcs, wcss)):
+        cw = CWcs(w)
+        keep.append(cw)
+        frames[i].src = s.data_ptr()
+        frames[i].h = s.shape[0]
+        frames[i].w = s.shape[1]
+        frames[i].pitch = s.stride(0)
+        frames[i].wcs = cw.s
+    return frames, keep
+
+
+def reproject_batch(srcs: Sequence[torch.Tensor], src_wcss, tgt_wcs, shape_out, order="bilinear",
+                    *, outs=None, fps=None, footprint=True, cubic_a=-0.5, nan_outside=False,
+                    tile=0, autotune=False):
+    """Reproject many frames onto one target grid in one persistent launch.
+    Returns (outs, fps): lists of [H, W] float32 tensors."""
+    srcs = [_src_tensor(s) for s in srcs]
+    oh, ow = int(shape_out[0]), int(shape_out[1])
+    dev = srcs[0].device
+    if outs is None:
+        outs = [torch.empty((oh, ow), dtype=torch.float32, device=dev) for _ in srcs]
+    if footprint and fps is None:
+        fps = [torch.empty((oh, ow), dtype=torch.float32, device=dev) for _ in srcs]
+    frames, keep = _frames(srcs, src_wcss)
+    n = len(srcs)
+    out_ptrs = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    fp_ptrs = (C.c_void_p * n)(*[f.data_ptr() for f in fps]) if footprint else None
+    tw = CWcs(tgt_wcs)
+    o = _opts("f32", cubic_a, nan_outside, tile)
+    if autotune:
+        s, t = _lib.dfr_autotune_batch(n, frames, tw.s, oh, ow, ORDERS[order], out_ptrs, fp_ptrs,
+                                       o, _stream(dev))
+        _check(s, "dfr_autotune_batch")
+    s = _lib.dfr_reproject_batch(n, frames, tw.s, oh, ow, ORDERS[order], out_ptrs, fp_ptrs, o,
+                                 _stream(dev))
+    _check(s, "dfr_reproject_batch")
+    return outs, (fps if footprint else None)
+
+
+def autotune(src, src_wcs, tgt_wcs, shape_out, order="bilinear", cubic_a=-0.5) -> int:
+    """Time every tile shape for this reprojection and cache the fastest."""
+    src = _src_tensor(src)
+    oh, ow = int(shape_out[0]), int(shape_out[1])
+    out = torch.empty((oh, ow), dtype=torch.float32, device=src.device)
+    fp = torch.empty_like(out)
+    sw, tw = CWcs(src_wcs), CWcs(tgt_wcs)
+    s, t = _lib.dfr_autotune(src.data_ptr(), src.shape[0], src.shape[1], src.stride(0), sw.s, tw.s,
+                             oh, ow, ORDERS[order], out.data_ptr(), fp.data_ptr(),
+                             _opts("f32", cubic_a), _stream(src.device))
+    _check(s, "dfr_autotune")
+    return t
+
+
+# ------------------------------------------------------------ gradients --
+
+def wcs_params(w) -> np.ndarray:
+    """Source-WCS parameter vector in the gradient order of the C ABI:
+    CRVAL(2), CRPIX(2), CD(4), AP[(o+1)^2], BP[(o+1)^2]."""
+    w = as_wcs(w)
+    parts = [np.asarray(w.crval, float), np.asarray(w.crpix, float),
+             np.asarray(w.cd, float).ravel()]
+    for c in (w.ap, w.bp):
+        if c is not None:
+            parts.append(np.asarray(c, float).ravel())
+    return np.concatenate(parts)
+
+
+def wcs_with_params(template, theta) -> Wcs:
+    """The template WCS with the parameters of :func:`wcs_params` replaced."""
+    t = np.asarray(theta, dtype=np.float64)
+    w = as_wcs(template)
+    ap = bp = None
+    k = 8
+    if w.ap is not None:
+        n = w.ap.shape[0]
+        ap = t[k:k + n * n].reshape(n, n)
+        k += n * n
+    if w.bp is not None:
+        n = w.bp.shape[0]
+        bp = t[k:k + n * n].reshape(n, n)
+        k += n * n
+    return Wcs((t[2], t[3]), (t[0], t[1]), t[4:8].reshape(2, 2), w.a, w.b, ap, bp)
+
+
+def reproject_backward(src, src_wcs, tgt_wcs, shape_out, order, grad_out, *, want_src=True,
+                       want_wcs=True, cubic_a=-0.5, tile=0):
+    """(grad_src float32 [H, W] or None, grad_wcs float64 [n] or None)."""
+    src = _src_tensor(src)
+    oh, ow = int(shape_out[0]), int(shape_out[1])
+    sw, tw = CWcs(src_wcs), CWcs(tgt_wcs)
+    gs = torch.empty(src.shape, dtype=torch.float32, device=src.device) if want_src else None
+    gw = torch.empty(_lib.dfr_wcs_grad_size(sw.s), dtype=torch.float64,
+                     device=src.device) if want_wcs else None
+    g = grad_out.contiguous().float()
+    s = _lib.dfr_reproject_backward(src.data_ptr(), src.shape[0], src.shape[1], src.stride(0),
+                                    sw.s, tw.s, oh, ow, ORDERS[order], g.data_ptr(), _ptr(gs),
+                                    _ptr(gw), _opts("f32", cubic_a, tile=tile),
+                                    _stream(src.device))
+    _check(s, "dfr_reproject_backward")
+    return gs, gw
+
+
+class ReprojectFn(torch.autograd.Function):
+    """out = reproject(src, WCS(theta)); differentiable in src and theta
+    (theta as in :func:`wcs_params`, float64)."""
+
+    @staticmethod
+    def forward(ctx, src, theta, template, tgt_wcs, shape_out, order, cubic_a):
+        w = wcs_with_params(template, theta.detach().cpu().numpy())
+        out, _ = reproject(src, w, tgt_wcs, shape_out, order, footprint=False, cubic_a=cubic_a)
+        ctx.save_for_backward(src)
+        ctx.cfg = (w, tgt_wcs, shape_out, order, cubic_a, theta.device)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (src,) = ctx.saved_tensors
+        w, tgt, shape_out, order, a, tdev = ctx.cfg
+        gs, gw = reproject_backward(src, w, tgt, shape_out, order, grad_out,
+                                    want_src=ctx.needs_input_grad[0],
+                                    want_wcs=ctx.needs_input_grad[1], cubic_a=a)
+        return gs, (gw.to(tdev) if gw is not None else None), None, None, None, None, None
+
+
+def reproject_differentiable(src, theta, template, tgt_wcs, shape_out, order="bicubic",
+                             cubic_a=-0.5):
+    return ReprojectFn.apply(src, theta, template, tgt_wcs, shape_out, order, cubic_a)
+
+
+def sq_residual(out, ref, mask=None, want_grad=True):
+    """(loss [1] float64 tensor, grad_out or None) with
+    loss = sum mask*(out-ref)^2 and grad_out = 2*mask*(out-ref)."""
+    out = out.contiguous()
+    ref = ref.contiguous()
+    n = out.numel()
+    loss = torch.empty(1, dtype=torch.float64, device=out.device)
+    g = torch.empty_like(out) if want_grad else None
+    m = mask.contiguous().float() if mask is not None else None
+    s = _lib.dfr_sq_residual(out.data_ptr(), ref.data_ptr(), _ptr(m), n, loss.data_ptr(),
+                             _ptr(g), _stream(out.device))
+    _check(s, "dfr_sq_residual")
+    return loss, g
+
+
+def release():
+    _check(_lib.dfr_release(), "dfr_release")

@@ -1,0 +1,393 @@
+// extern "C" entry points of libdfr (declared in include/dfr.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "dfr.h"
+#include "launch.hpp"
+#include "plan.hpp"
+#include "runtime.hpp"
+
+using namespace dfr;
+
+namespace {
+
+dfr_status resolve_options(const dfr_options *opt, dfr_options &o) {
+  dfr_options_init(&o);
+  if (!opt) return DFR_OK;
+  if (opt->size != sizeof(dfr_options)) return DFR_E_ARG;
+  o = *opt;
+  if (o.precision < DFR_PREC_F32 || o.precision > DFR_PREC_TRIG_F64) return DFR_E_UNSUPPORTED;
+  if (!std::isfinite(o.cubic_a)) return DFR_E_ARG;
+  if (o.tile < 0 || o.tile > kTileCount) return DFR_E_ARG;
+  return DFR_OK;
+}
+
+bool interp_ok(int interp) {
+  return interp == DFR_NEAREST || interp == DFR_BILINEAR || interp == DFR_BICUBIC;
+}
+
+// Argument checks shared by the single-image entry points.
+dfr_status check_single(const float *src, int32_t src_h, int32_t src_w, int64_t src_pitch,
+                        const dfr_wcs *src_wcs, const dfr_wcs *tgt_wcs, int32_t out_h,
+                        int32_t out_w, int interp) {
+  if (!src_wcs || !tgt_wcs) return DFR_E_NULL;
+  if (src_h < 0 || src_w < 0 || out_h < 0 || out_w < 0) return DFR_E_SHAPE;
+  if (src_h > 0 && src_w > 0) {
+    if (!src) return DFR_E_NULL;
+    if (src_pitch < src_w) return DFR_E_SHAPE;
+  }
+  dfr_status s;
+  if ((s = check_wcs(src_wcs, true)) != DFR_OK) return s;
+  if ((s = check_wcs(tgt_wcs, false)) != DFR_OK) return s;
+  if (!interp_ok(interp)) return DFR_E_UNSUPPORTED;
+  return DFR_OK;
+}
+
+// Batch tune key: the interpolation, the padded SIP order, the frame count
+// and the output size class (frames of a stack differ in rotation and scale).
+std::string batch_key(const std::vector<FramePlan> &plans, int32_t out_h, int32_t out_w,
+                      int interp, int max_sord) {
+  char key[128];
+  int mb = (int)std::lround(std::log2(std::max(1.0, (double)out_h * out_w)));
+  std::snprintf(key, sizeof(key), "batch:i%d:s%d:n%d:o%d", interp, std::min(max_sord, 6),
+                (int)plans.size(), mb);
+  return key;
+}
+
+// Geometry for a batch with tile `t`: the LDS budget covers the largest
+// estimated source box over the frames.
+void batch_geom(const std::vector<FramePlan> &plans, int32_t out_h, int32_t out_w, int interp,
+                int t, const dfr_options &o, TileGeom &G, int &np) {
+  TileShape ts;
+  make_geom(plans[0], out_h, out_w, interp, t, o, G, ts);
+  int64_t need = 0;
+  for (auto &P : plans) need = std::max<int64_t>(need, estimate_lds_floats(P, out_h, out_w, ts, interp));
+  G.lds_cap = need <= kLdsMaxFloats ? (int32_t)need : 0;
+  np = ts.np;
+}
+
+dfr_status prepare_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_wcs,
+                         int32_t out_h, int32_t out_w, int interp, float *const *outs,
+                         float *const *footprints, const dfr_options *opt,
+                         std::vector<FramePlan> &plans, TileGeom &G, int &tile, int &np,
+                         int &max_sord) {
+  if (n < 0) return DFR_E_ARG;
+  if (n > 0 && (!frames || !outs)) return DFR_E_NULL;
+  if (!tgt_wcs) return DFR_E_NULL;
+  if (out_h < 0 || out_w < 0) return DFR_E_SHAPE;
+  if (!interp_ok(interp)) return DFR_E_UNSUPPORTED;
+  dfr_status s;
+  if ((s = check_wcs(tgt_wcs, false)) != DFR_OK) return s;
+  dfr_options o;
+  if ((s = resolve_options(opt, o)) != DFR_OK) return s;
+  if (o.precision != DFR_PREC_F32) return DFR_E_UNSUPPORTED;
+  if (o.debug_positions) return DFR_E_ARG;
+  if ((int64_t)n * (((int64_t)out_h * out_w + 1023) / 1024) > 0x7fffffffLL) return DFR_E_SHAPE;
+  for (int i = 0; i < n; ++i) {
+    const dfr_frame &f = frames[i];
+    if (f.h < 0 || f.w < 0) return DFR_E_SHAPE;
+    if (f.h > 0 && f.w > 0) {
+      if (!f.src) return DFR_E_NULL;
+      if (f.pitch < f.w) return DFR_E_SHAPE;
+    }
+    if ((s = check_wcs(&f.wcs, true)) != DFR_OK) return s;
+    if ((int64_t)out_h * out_w > 0 && !outs[i]) return DFR_E_NULL;
+  }
+  plans.clear();
+  if (n == 0 || out_h == 0 || out_w == 0) {
+    std::memset(&G, 0, sizeof(G));
+    return DFR_OK;
+  }
+  plans.resize(n);
+  max_sord = 0;
+  for (int i = 0; i < n; ++i) {
+    const dfr_frame &f = frames[i];
+    const float *src = (f.h > 0 && f.w > 0) ? f.src : nullptr;
+    build_plan(src, f.h, f.w, f.pitch, f.wcs, *tgt_wcs, out_h, out_w, outs[i],
+               footprints ? footprints[i] : nullptr, plans[i]);
+    max_sord = std::max(max_sord, plans[i].s_order);
+  }
+  if (max_sord > 5) max_sord = 6;  // run-time order kernel
+  tile = o.tile;
+  if (tile == 0) {
+    std::lock_guard<std::mutex> lk(tune_mutex_for_batch());
+    tile = tuned_tile(batch_key(plans, out_h, out_w, interp, max_sord));
+  }
+  if (tile == 0) tile = kDefaultTile;
+  batch_geom(plans, out_h, out_w, interp, tile, o, G, np);
+  return DFR_OK;
+}
+
+// Time every tile shape (two warm launches, then the best of three timed
+// ones) and return the fastest in `best`.
+template <typename Run>
+dfr_status time_candidates(Run &run, hipStream_t st, int &best) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DFR_E_DEVICE;
+  float best_ms = 1e30f;
+  best = kDefaultTile;
+  dfr_status status = DFR_OK;
+  for (int t = 1; t <= kTileCount && status == DFR_OK; ++t) {
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 5; ++rep) {
+      float ms = 0.0f;
+      if (hipEventRecord(e0, st) != hipSuccess || !run(t) || hipEventRecord(e1, st) != hipSuccess ||
+          hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        status = DFR_E_DEVICE;
+        break;
+      }
+      if (rep >= 2) ms_min = std::min(ms_min, ms);
+    }
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dfr_options_init(dfr_options *opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->size = sizeof(dfr_options);
+  opt->precision = DFR_PREC_F32;
+  opt->cubic_a = -0.5;
+  opt->nan_outside = 0;
+  opt->tile = 0;
+  opt->debug_positions = nullptr;
+}
+
+dfr_status dfr_reproject(const float *src, int32_t src_h, int32_t src_w, int64_t src_pitch,
+                         const dfr_wcs *src_wcs, const dfr_wcs *tgt_wcs, int32_t out_h,
+                         int32_t out_w, dfr_interp interp, float *out, float *footprint,
+                         const dfr_options *opt, void *stream) {
+  dfr_status s = check_single(src, src_h, src_w, src_pitch, src_wcs, tgt_wcs, out_h, out_w,
+                              (int)interp);
+  if (s != DFR_OK) return s;
+  dfr_options o;
+  if ((s = resolve_options(opt, o)) != DFR_OK) return s;
+  if (out_h == 0 || out_w == 0) return DFR_OK;
+  if (!out) return DFR_E_NULL;
+  if (src_h == 0 || src_w == 0) src = nullptr;
+  FramePlan P;
+  build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, out, footprint, P);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (o.precision == DFR_PREC_F32) {
+    TileGeom G;
+    TileShape ts;
+    int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false);
+    make_geom(P, out_h, out_w, (int)interp, tile, o, G, ts);
+    e = launch_forward_f32(P, G, (int)interp, ts.np, st);
+  } else {
+    TrigPlan T;
+    build_trig_plan(*src_wcs, *tgt_wcs, T);
+    TileGeom G;
+    TileShape ts;
+    make_geom(P, out_h, out_w, (int)interp, kDefaultTile, o, G, ts);
+    e = launch_forward_f64(P, T, G, (int)interp, o.precision == DFR_PREC_TRIG_F64, st);
+  }
+  return e == hipSuccess ? DFR_OK : DFR_E_DEVICE;
+}
+
+dfr_status dfr_reproject_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_wcs,
+                               int32_t out_h, int32_t out_w, dfr_interp interp,
+                               float *const *outs, float *const *footprints,
+                               const dfr_options *opt, void *stream) {
+  std::vector<FramePlan> plans;
+  int tile = 0, np = 0, max_sord = 0;
+  TileGeom G;
+  dfr_status s = prepare_batch(n, frames, tgt_wcs, out_h, out_w, (int)interp, outs, footprints,
+                               opt, plans, G, tile, np, max_sord);
+  if (s != DFR_OK || plans.empty() || G.n_tiles == 0) return s;
+  return run_batch(plans, G, (int)interp, np, max_sord, reinterpret_cast<hipStream_t>(stream),
+                   true);
+}
+
+dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w,
+                                  int64_t src_pitch, const dfr_wcs *src_wcs,
+                                  const dfr_wcs *tgt_wcs, int32_t out_h, int32_t out_w,
+                                  dfr_interp interp, const float *grad_out, float *grad_src,
+                                  double *grad_wcs, const dfr_options *opt, void *stream) {
+  dfr_status s = check_single(src, src_h, src_w, src_pitch, src_wcs, tgt_wcs, out_h, out_w,
+                              (int)interp);
+  if (s != DFR_OK) return s;
+  dfr_options o;
+  if ((s = resolve_options(opt, o)) != DFR_OK) return s;
+  if (o.precision != DFR_PREC_F32) return DFR_E_UNSUPPORTED;
+  if (std::max(src_wcs->ap_order, src_wcs->bp_order) > 5) return DFR_E_UNSUPPORTED;
+  if ((int64_t)out_h * out_w > 0 && !grad_out) return DFR_E_NULL;
+  if (src_h == 0 || src_w == 0) src = nullptr;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (grad_src && src_h > 0 && src_w > 0 &&
+      launch_zero_f32(grad_src, src_h, src_w, src_w, st) != hipSuccess)
+    return DFR_E_DEVICE;
+  FramePlan P;
+  build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, nullptr, nullptr, P);
+  o.debug_positions = nullptr;
+  TileGeom G;
+  TileShape ts;
+  std::memset(&G, 0, sizeof(G));
+  if (out_h > 0 && out_w > 0) {
+    int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false, 2);
+    make_geom(P, out_h, out_w, (int)interp, tile, o, G, ts, 2);
+  }
+  const int ns = backward_sums(P.s_order);
+  WcsJacobian J;
+  h_jacobian(*src_wcs, *tgt_wcs, J.dh);
+  std::lock_guard<std::mutex> lk(workspace_mutex());
+  Workspace *w = workspace(st);
+  size_t bytes = ((size_t)std::max(G.n_tiles, 1) * ns + ns) * sizeof(double);
+  double *part = static_cast<double *>(workspace_buffer(w, bytes));
+  if (!part) return DFR_E_NOMEM;
+  double *totals = part + (size_t)std::max(G.n_tiles, 1) * ns;
+  if (G.n_tiles > 0 &&
+      launch_backward(P, G, (int)interp, ts.np, grad_out, grad_src, src_w, part, st) != hipSuccess)
+    return DFR_E_DEVICE;
+  if (launch_backward_finish(part, G.n_tiles, ns, totals, J, P.s_order, src_wcs->ap_order,
+                             src_wcs->bp_order, P.s_scale, grad_wcs, st) != hipSuccess)
+    return DFR_E_DEVICE;
+  return DFR_OK;
+}
+
+dfr_status dfr_sq_residual(const float *out, const float *ref, const float *mask, int64_t n,
+                           double *loss, float *grad_out, void *stream) {
+  if (n < 0) return DFR_E_SHAPE;
+  if (!loss || (n > 0 && (!out || !ref))) return DFR_E_NULL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+  std::lock_guard<std::mutex> lk(workspace_mutex());
+  double *part = static_cast<double *>(workspace_buffer(workspace(st), blocks * sizeof(double)));
+  if (!part) return DFR_E_NOMEM;
+  return launch_sq_residual(out, ref, mask, n, part, blocks, loss, grad_out, st) == hipSuccess
+             ? DFR_OK
+             : DFR_E_DEVICE;
+}
+
+dfr_status dfr_autotune(const float *src, int32_t src_h, int32_t src_w, int64_t src_pitch,
+                        const dfr_wcs *src_wcs, const dfr_wcs *tgt_wcs, int32_t out_h,
+                        int32_t out_w, dfr_interp interp, float *out, float *footprint,
+                        const dfr_options *opt, void *stream, int32_t *tile) {
+  dfr_status s = check_single(src, src_h, src_w, src_pitch, src_wcs, tgt_wcs, out_h, out_w,
+                              (int)interp);
+  if (s != DFR_OK) return s;
+  dfr_options o;
+  if ((s = resolve_options(opt, o)) != DFR_OK) return s;
+  if (o.precision != DFR_PREC_F32) return DFR_E_UNSUPPORTED;
+  if (out_h == 0 || out_w == 0 || src_h == 0 || src_w == 0) {
+    if (tile) *tile = kDefaultTile;
+    return DFR_OK;
+  }
+  if (!out) return DFR_E_NULL;
+  o.debug_positions = nullptr;
+  FramePlan P;
+  build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, out, footprint, P);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  auto run = [&](int t) -> bool {
+    TileGeom G;
+    TileShape ts;
+    make_geom(P, out_h, out_w, (int)interp, t, o, G, ts);
+    return launch_forward_f32(P, G, (int)interp, ts.np, st) == hipSuccess;
+  };
+  int best = 0;
+  s = time_candidates(run, st, best);
+  if (s != DFR_OK) return s;
+  tune_store(tune_key(P, out_h, out_w, (int)interp, false), best);
+  if (tile) *tile = best;
+  return DFR_OK;
+}
+
+dfr_status dfr_autotune_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_wcs,
+                              int32_t out_h, int32_t out_w, dfr_interp interp,
+                              float *const *outs, float *const *footprints,
+                              const dfr_options *opt, void *stream, int32_t *tile) {
+  std::vector<FramePlan> plans;
+  int t0 = 0, np = 0, max_sord = 0;
+  TileGeom G;
+  dfr_status s = prepare_batch(n, frames, tgt_wcs, out_h, out_w, (int)interp, outs, footprints,
+                               opt, plans, G, t0, np, max_sord);
+  if (s != DFR_OK) return s;
+  if (plans.empty() || G.n_tiles == 0) {
+    if (tile) *tile = kDefaultTile;
+    return DFR_OK;
+  }
+  dfr_options o;
+  resolve_options(opt, o);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  auto run = [&](int t) -> bool {
+    TileGeom Gt;
+    int npt = 0;
+    batch_geom(plans, out_h, out_w, (int)interp, t, o, Gt, npt);
+    return run_batch(plans, Gt, (int)interp, npt, max_sord, st, false) == DFR_OK;
+  };
+  int best = 0;
+  s = time_candidates(run, st, best);
+  if (s != DFR_OK) return s;
+  tune_store(batch_key(plans, out_h, out_w, (int)interp, max_sord), best);
+  if (tile) *tile = best;
+  return DFR_OK;
+}
+
+dfr_status dfr_release(void) {
+  release_workspaces();
+  return DFR_OK;
+}
+
+int64_t dfr_wcs_grad_size(const dfr_wcs *w) {
+  if (!w) return 0;
+  int64_t na = w->ap_order > 0 ? (int64_t)(w->ap_order + 1) * (w->ap_order + 1) : 0;
+  int64_t nb = w->bp_order > 0 ? (int64_t)(w->bp_order + 1) * (w->bp_order + 1) : 0;
+  return 8 + na + nb;
+}
+
+int32_t dfr_tile_count(void) { return kTileCount; }
+
+dfr_status dfr_tile_shape(int32_t tile, int32_t *width, int32_t *height) {
+  TileShape s;
+  if (!tile_shape(tile, s)) return DFR_E_ARG;
+  if (width) *width = s.width;
+  if (height) *height = s.height;
+  return DFR_OK;
+}
+
+void dfr_cd_from_pc_cdelt(const double pc[4], const double cdelt[2], double cd[4]) {
+  if (!pc || !cdelt || !cd) return;
+  cd[0] = cdelt[0] * pc[0];
+  cd[1] = cdelt[0] * pc[1];
+  cd[2] = cdelt[1] * pc[2];
+  cd[3] = cdelt[1] * pc[3];
+}
+
+dfr_status dfr_check_wcs(const dfr_wcs *wcs, int32_t as_source) {
+  return check_wcs(wcs, as_source != 0);
+}
+
+const char *dfr_strerror(dfr_status s) {
+  switch (s) {
+    case DFR_OK: return "success";
+    case DFR_E_NULL: return "a required pointer is NULL";
+    case DFR_E_SHAPE: return "invalid image shape or pitch";
+    case DFR_E_WCS: return "invalid WCS (non-finite value, singular CD, |Dec| > 90, or bad SIP)";
+    case DFR_E_UNSUPPORTED: return "unsupported interpolation, precision or WCS form";
+    case DFR_E_DEVICE: return "HIP runtime or kernel launch failure";
+    case DFR_E_NOMEM: return "out of memory";
+    case DFR_E_ARG: return "invalid argument";
+  }
+  return "unknown status";
+}
+
+int32_t dfr_abi_version(void) { return DFR_ABI_VERSION; }
+
+}  // extern "C"

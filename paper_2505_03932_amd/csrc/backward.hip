@@ -1,0 +1,375 @@
+// Backward pass of the FP32 reprojection (not in the paper: it turns the
+// reprojection into a differentiable step so WCS alignment can be refined
+// by gradient descent on image residuals).
+//
+// For a loss L with g = dL/dout:
+//   dL/dsrc_k = sum_p g_p w_kp / F_p       -- adjoint of the interpolation, a
+//                                            scatter-add: taps accumulate in
+//                                            an LDS copy of the tile's source
+//                                            box (ds_add_f32), which is then
+//                                            flushed with one global atomic
+//                                            per touched source pixel;
+//   dL/dpos_p  = g_p (dS/dpos - out dF/dpos) / F
+// and through the map pos = (U, V) + SIP(U, V) + CRPIX - 1 with
+// (U, V) = (p/w, q/w), (p, q, w) = H t:
+//   dL/dH_1j = sum a t_j / w,  dL/dH_2j = sum b t_j / w,
+//   dL/dH_3j = -sum (a U + b V) t_j / w,
+// a = dL/dU, b = dL/dV; plus dL/dCRPIX and the AP/BP monomial sums.  These
+// are reduced per wave, then per work-group into FP64 partials, then in a
+// fixed order (deterministic), and chained to CRVAL and CD on the device
+// with the FP64 Jacobian dH/d(CRVAL, CD) composed on the host.
+#include "forward_body.hpp"
+#include "launch.hpp"
+
+namespace dfr {
+
+template <int INTERP, typename Fetch, typename Scatter>
+__device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float ry, int W, int H,
+                                                float a, float g, const Fetch &fetch,
+                                                const Scatter &scatter, float &gx, float &gy) {
+  gx = 0.0f;
+  gy = 0.0f;
+  if constexpr (INTERP == DFR_NEAREST) {
+    int i = bx + (int)rintf(rx), j = by + (int)rintf(ry);
+    bool in = ((unsigned)i < (unsigned)W) && ((unsigned)j < (unsigned)H);
+    if (in) scatter(i, j, g);
+    return in;
+  } else {
+    constexpr int NT = INTERP == DFR_BILINEAR ? 2 : 4;
+    float fx = floorf(rx), fy = floorf(ry);
+    float t = rx - fx, s = ry - fy;
+    int i0 = bx + (int)fx - (NT == 4 ? 1 : 0), j0 = by + (int)fy - (NT == 4 ? 1 : 0);
+    float wx[4], wy[4], dx[4], dy[4];
+    if constexpr (NT == 2) {
+      wx[0] = 1.0f - t; wx[1] = t; dx[0] = -1.0f; dx[1] = 1.0f;
+      wy[0] = 1.0f - s; wy[1] = s; dy[0] = -1.0f; dy[1] = 1.0f;
+    } else {
+      keys_weights(t, a, wx);
+      keys_weights(s, a, wy);
+      keys_dweights(t, a, dx);
+      keys_dweights(s, a, dy);
+    }
+    bool inx[NT], iny[NT];
+    bool all_in = true;
+    float Fx = 0.0f, Fy = 0.0f, dFx = 0.0f, dFy = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      inx[k] = (unsigned)(i0 + k) < (unsigned)W;
+      iny[k] = (unsigned)(j0 + k) < (unsigned)H;
+      all_in = all_in && inx[k] && iny[k];
+      wx[k] = inx[k] ? wx[k] : 0.0f;
+      dx[k] = inx[k] ? dx[k] : 0.0f;
+      wy[k] = iny[k] ? wy[k] : 0.0f;
+      dy[k] = iny[k] ? dy[k] : 0.0f;
+      Fx += wx[k];
+      Fy += wy[k];
+      dFx += dx[k];
+      dFy += dy[k];
+    }
+    float F = all_in ? 1.0f : Fx * Fy;
+    if (!(F > 0.0f)) return false;
+    float iF = all_in ? 1.0f : __builtin_amdgcn_rcpf(F);
+    float c = g * iF;
+    float S = 0.0f, Sx = 0.0f, Sy = 0.0f;
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+      float row = 0.0f, rowd = 0.0f;
+#pragma unroll
+      for (int k = 0; k < NT; ++k) {
+        if (inx[k] && iny[l]) {
+          float v = fetch(i0 + k, j0 + l);
+          row = fmaf(wx[k], v, row);
+          rowd = fmaf(dx[k], v, rowd);
+          scatter(i0 + k, j0 + l, c * wx[k] * wy[l]);
+        }
+      }
+      S = fmaf(wy[l], row, S);
+      Sx = fmaf(wy[l], rowd, Sx);
+      Sy = fmaf(dy[l], row, Sy);
+    }
+    float out = S * iF;
+    float Fdx = all_in ? 0.0f : dFx * Fy, Fdy = all_in ? 0.0f : Fx * dFy;
+    gx = g * (Sx - out * Fdx) * iF;
+    gy = g * (Sy - out * Fdy) * iF;
+    return true;
+  }
+}
+
+template <int INTERP, int SORD, int NP>
+__global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom G,
+                                                          const float *__restrict__ gout,
+                                                          float *__restrict__ gsrc,
+                                                          int64_t gpitch,
+                                                          double *__restrict__ partials) {
+  constexpr int NC = (SORD + 1) * (SORD + 2) / 2;
+  constexpr int NS = 11 + 2 * NC;
+  extern __shared__ float lds[];
+  __shared__ TileShared sh;
+  __shared__ float wsum[kThreads / 64][NS];
+  const int tile = xcd_tile(blockIdx.x, G.n_tiles);
+  const int tid = threadIdx.x;
+  float acc[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) acc[s] = 0.0f;
+
+  TileCtx c;
+  if (tile_anchors<INTERP, NP>(P, G, tile, sh, c)) {
+    TilePos<NP> T;
+    tile_positions<INTERP, SORD, NP>(P, G, sh, c, T);
+    const int bw = T.empty ? 0 : T.bi1 - T.bi0 + 1;
+    const int bh = T.empty ? 0 : T.bj1 - T.bj0 + 1;
+    const bool use_lds = !T.empty && 2 * (int64_t)bw * bh <= (int64_t)G.lds_cap;
+    float *vals = lds;
+    float *gacc = lds + (use_lds ? bw * bh : 0);
+    if (use_lds) {
+      stage_box(P, T.bi0, T.bj0, bw, bh, vals);
+      for (int i = tid; i < bw * bh; i += kThreads) gacc[i] = 0.0f;
+    }
+    __syncthreads();
+    const int W = P.src_w, Hs = P.src_h;
+    const int bi0 = T.bi0, bj0 = T.bj0;
+    auto fetch_lds = [&](int i, int j) -> float { return vals[(j - bj0) * bw + (i - bi0)]; };
+    auto fetch_glb = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
+    auto scat_lds = [&](int i, int j, float v) { atomicAdd(&gacc[(j - bj0) * bw + (i - bi0)], v); };
+    auto scat_glb = [&](int i, int j, float v) {
+      if (gsrc) atomicAdd(&gsrc[(int64_t)j * gpitch + i], v);
+    };
+    const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
+    const float S_s = (float)P.s_scale;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int y = c.y0 + c.ty + k * c.RP;
+#pragma unroll
+      for (int e = 0; e < kRun; ++e) {
+        if (!(T.valid & (1u << (k * kRun + e)))) continue;
+        const int x = c.xr + e;
+        const float g = gout[(int64_t)y * G.out_w + x];
+        if (g == 0.0f) continue;
+        float gx, gy;
+        bool cov;
+        if (use_lds)
+          cov = interp_backward<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs,
+                                        G.cubic_a, g, fetch_lds, scat_lds, gx, gy);
+        else
+          cov = interp_backward<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs,
+                                        G.cubic_a, g, fetch_glb, scat_glb, gx, gy);
+        if constexpr (INTERP != DFR_NEAREST) {
+          if (!cov) continue;
+          const Anchor &A = sh.anchor[T.aidx[k]];
+          PixelGeom pg;
+          float px, py;
+          pixel_position<SORD>(P, A, tinv, sinv, (float)((c.xr & (kCell - 1)) + e),
+                               (float)(y & (kCell - 1)), px, py, &pg);
+          float fa, fau, fav, fb, fbu, fbv;
+          sip_f32_grad<SORD>(P.fsA, pg.us, pg.vs, fa, fau, fav);
+          sip_f32_grad<SORD>(P.fsB, pg.us, pg.vs, fb, fbu, fbv);
+          const float da = gx * fmaf(fau, sinv, 1.0f) + gy * (fbu * sinv);  // dL/dU
+          const float db = gx * (fav * sinv) + gy * fmaf(fbv, sinv, 1.0f);  // dL/dV
+          const float U = pg.us * S_s, V = pg.vs * S_s;
+          const float iw = A.inv_w0 * pg.r;
+          const float t0 = A.tu0 + pg.du, t1 = A.tv0 + pg.dv;
+          const float a1 = da * iw, b1 = db * iw, c1 = -(da * U + db * V) * iw;
+          acc[0] = fmaf(a1, t0, acc[0]);
+          acc[1] = fmaf(a1, t1, acc[1]);
+          acc[2] += a1;
+          acc[3] = fmaf(b1, t0, acc[3]);
+          acc[4] = fmaf(b1, t1, acc[4]);
+          acc[5] += b1;
+          acc[6] = fmaf(c1, t0, acc[6]);
+          acc[7] = fmaf(c1, t1, acc[7]);
+          acc[8] += c1;
+          acc[9] += gx;
+          acc[10] += gy;
+          if constexpr (SORD > 0) {
+            float up = 1.0f;
+#pragma unroll
+            for (int p = 0; p <= SORD; ++p) {
+              float m = up;
+#pragma unroll
+              for (int q = 0; p + q <= SORD; ++q) {
+                acc[11 + tri_n(SORD, p, q)] = fmaf(gx, m, acc[11 + tri_n(SORD, p, q)]);
+                acc[11 + NC + tri_n(SORD, p, q)] = fmaf(gy, m, acc[11 + NC + tri_n(SORD, p, q)]);
+                m *= pg.vs;
+              }
+              up *= pg.us;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (use_lds && gsrc) {
+      const int wave = tid >> 6, lane = tid & 63;
+      for (int r = wave; r < bh; r += kThreads / 64)
+        for (int col = lane; col < bw; col += 64) {
+          float v = gacc[r * bw + col];
+          if (v != 0.0f) atomicAdd(&gsrc[(int64_t)(bj0 + r) * gpitch + bi0 + col], v);
+        }
+    }
+  }
+  // per-wave, then per-group sums of the WCS terms (skipped tiles give 0)
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    float v = wave_sum(acc[s]);
+    if ((tid & 63) == 0) wsum[tid >> 6][s] = v;
+  }
+  __syncthreads();
+  if (tid < NS) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) t += (double)wsum[w][tid];
+    partials[(int64_t)tile * NS + tid] = t;
+  }
+}
+
+using BwdKernel = void (*)(FramePlan, TileGeom, const float *, float *, int64_t, double *);
+
+template <int INTERP, int NP>
+static BwdKernel bwd_sord(int sord) {
+  switch (sord) {
+    case 0: return reproject_bwd<INTERP, 0, NP>;
+    case 1: return reproject_bwd<INTERP, 1, NP>;
+    case 2: return reproject_bwd<INTERP, 2, NP>;
+    case 3: return reproject_bwd<INTERP, 3, NP>;
+    case 4: return reproject_bwd<INTERP, 4, NP>;
+    default: return reproject_bwd<INTERP, 5, NP>;
+  }
+}
+
+template <int INTERP>
+static BwdKernel bwd_np(int np, int sord) {
+  switch (np) {
+    case 1: return bwd_sord<INTERP, 1>(sord);
+    case 2: return bwd_sord<INTERP, 2>(sord);
+    default: return bwd_sord<INTERP, 4>(sord);
+  }
+}
+
+hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, int np,
+                           const float *grad_out, float *grad_src, int64_t gsrc_pitch,
+                           double *partials, hipStream_t stream) {
+  if (G.n_tiles <= 0) return hipSuccess;
+  BwdKernel k = interp == DFR_NEAREST    ? bwd_np<DFR_NEAREST>(np, P.s_order)
+                : interp == DFR_BILINEAR ? bwd_np<DFR_BILINEAR>(np, P.s_order)
+                                         : bwd_np<DFR_BICUBIC>(np, P.s_order);
+  size_t lds = (size_t)G.lds_cap * sizeof(float);
+  hipLaunchKernelGGL(k, dim3(G.n_tiles), dim3(kThreads), lds, stream, P, G, grad_out, grad_src,
+                     gsrc_pitch, partials);
+  return hipGetLastError();
+}
+
+// Column s of the [n_blocks][ns] partials, summed in a fixed order.
+__global__ __launch_bounds__(256) void bwd_reduce(const double *__restrict__ partials,
+                                                  int n_blocks, int ns,
+                                                  double *__restrict__ totals) {
+  __shared__ double sm[256];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  double a = 0.0;
+  for (int b = tid; b < n_blocks; b += 256) a += partials[(int64_t)b * ns + s];
+  sm[tid] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) sm[tid] += sm[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) totals[s] = sm[0];
+}
+
+// Chain rule to the source WCS parameters, in the order of
+// dfr_wcs_grad_size: CRVAL(2), CRPIX(2), CD(4), AP, BP (square layouts).
+__global__ void bwd_chain(const double *__restrict__ totals, WcsJacobian J, int s_order,
+                          int ap_order, int bp_order, double S, double *__restrict__ grad) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int NC = (s_order + 1) * (s_order + 2) / 2;
+  for (int k = 0; k < 2; ++k) {
+    double g = 0.0;
+    for (int i = 0; i < 9; ++i) g += totals[i] * J.dh[k * 9 + i];
+    grad[k] = g;
+  }
+  grad[2] = totals[9];
+  grad[3] = totals[10];
+  for (int kl = 0; kl < 4; ++kl) {
+    double g = 0.0;
+    for (int i = 0; i < 9; ++i) g += totals[i] * J.dh[(2 + kl) * 9 + i];
+    grad[4 + kl] = g;
+  }
+  int off = 8;
+  const int orders[2] = {ap_order, bp_order};
+  for (int poly = 0; poly < 2; ++poly) {
+    const int o = orders[poly];
+    if (o <= 0) continue;
+    for (int p = 0; p <= o; ++p)
+      for (int q = 0; q <= o; ++q) {
+        double v = 0.0;
+        if (p + q <= o) {
+          double sc = 1.0;
+          for (int i = 0; i < p + q; ++i) sc *= S;
+          v = totals[11 + poly * NC + tri_n(s_order, p, q)] * sc;
+        }
+        grad[off + p * (o + 1) + q] = v;
+      }
+    off += (o + 1) * (o + 1);
+  }
+}
+
+hipError_t launch_backward_finish(const double *partials, int n_blocks, int n_sums,
+                                  double *totals, const WcsJacobian &jac, int s_order,
+                                  int ap_order, int bp_order, double s_scale, double *grad_wcs,
+                                  hipStream_t stream) {
+  hipLaunchKernelGGL(bwd_reduce, dim3(n_sums), dim3(256), 0, stream, partials, n_blocks, n_sums,
+                     totals);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !grad_wcs) return e;
+  hipLaunchKernelGGL(bwd_chain, dim3(1), dim3(64), 0, stream, totals, jac, s_order, ap_order,
+                     bp_order, s_scale, grad_wcs);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ alignment loss
+
+__global__ __launch_bounds__(256) void sq_residual_kernel(const float *__restrict__ out,
+                                                          const float *__restrict__ ref,
+                                                          const float *__restrict__ mask,
+                                                          int64_t n, double *__restrict__ partials,
+                                                          float *__restrict__ gout) {
+  __shared__ double ws[4];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    float r = out[i] - ref[i];
+    float m = mask ? mask[i] : 1.0f;
+    acc += (double)m * (double)r * (double)r;
+    if (gout) gout[i] = 2.0f * m * r;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double *__restrict__ partials,
+                                                           int n, double *__restrict__ loss) {
+  __shared__ double sm[256];
+  double a = 0.0;
+  for (int b = threadIdx.x; b < n; b += 256) a += partials[b];
+  sm[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = sm[0];
+}
+
+hipError_t launch_sq_residual(const float *out, const float *ref, const float *mask, int64_t n,
+                              double *partials, int n_blocks, double *loss, float *grad_out,
+                              hipStream_t stream) {
+  hipLaunchKernelGGL(sq_residual_kernel, dim3(n_blocks), dim3(256), 0, stream, out, ref, mask, n,
+                     partials, grad_out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, stream, partials, n_blocks,
+                     loss);
+  return hipGetLastError();
+}
+
+}  // namespace dfr

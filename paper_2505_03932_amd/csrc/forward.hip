@@ -1,0 +1,253 @@
+// Forward reprojection kernels: the FP32 tiled path (FP64 anchors, FP32
+// per-pixel offsets, LDS-staged source tiles) and the two FP64 comparison
+// forms (composed projective map; explicit two-stage trigonometry of the
+// paper's section 3.2).
+#include "forward_body.hpp"
+#include "launch.hpp"
+
+namespace dfr {
+
+template <int INTERP, int SORD, int NP>
+__global__ __launch_bounds__(kThreads) void reproject_tiles(FramePlan P, TileGeom G) {
+  extern __shared__ float lds[];
+  __shared__ TileShared sh;
+  forward_tile<INTERP, SORD, NP>(P, G, xcd_tile(blockIdx.x, G.n_tiles), lds, sh);
+}
+
+using TileKernel = void (*)(FramePlan, TileGeom);
+
+template <int INTERP, int NP>
+static TileKernel pick_sord(int sord) {
+  switch (sord) {
+    case 0: return reproject_tiles<INTERP, 0, NP>;
+    case 1: return reproject_tiles<INTERP, 1, NP>;
+    case 2: return reproject_tiles<INTERP, 2, NP>;
+    case 3: return reproject_tiles<INTERP, 3, NP>;
+    case 4: return reproject_tiles<INTERP, 4, NP>;
+    case 5: return reproject_tiles<INTERP, 5, NP>;
+    default: return reproject_tiles<INTERP, kRtOrder, NP>;
+  }
+}
+
+template <int INTERP>
+static TileKernel pick_np(int np, int sord) {
+  switch (np) {
+    case 1: return pick_sord<INTERP, 1>(sord);
+    case 2: return pick_sord<INTERP, 2>(sord);
+    default: return pick_sord<INTERP, 4>(sord);
+  }
+}
+
+static TileKernel pick_tile_kernel(int interp, int np, int sord) {
+  switch (interp) {
+    case DFR_NEAREST: return pick_np<DFR_NEAREST>(np, sord);
+    case DFR_BILINEAR: return pick_np<DFR_BILINEAR>(np, sord);
+    default: return pick_np<DFR_BICUBIC>(np, sord);
+  }
+}
+
+hipError_t launch_forward_f32(const FramePlan &P, const TileGeom &G, int interp, int np,
+                              hipStream_t stream) {
+  if (G.n_tiles <= 0) return hipSuccess;
+  TileKernel k = pick_tile_kernel(interp, np, P.s_order);
+  size_t lds = (size_t)G.lds_cap * sizeof(float);
+  hipLaunchKernelGGL(k, dim3(G.n_tiles), dim3(kThreads), lds, stream, P, G);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ FP64 comparison forms
+
+// FP64 interpolation at (xs, ys) with zero padding; same rules as the FP32
+// path (interior footprint exactly 1, out = S/F where F > 0).
+template <int INTERP>
+__device__ __forceinline__ void interp_f64(const FramePlan &P, double xs, double ys, double a,
+                                           double &out, double &fp) {
+  const int W = P.src_w, H = P.src_h;
+  auto val = [&](int64_t i, int64_t j) -> double {
+    return (double)P.src[j * P.pitch + i];
+  };
+  if constexpr (INTERP == DFR_NEAREST) {
+    double fi = rint(xs), fj = rint(ys);
+    bool in = fi >= 0.0 && fi < W && fj >= 0.0 && fj < H;
+    out = in ? val((int64_t)fi, (int64_t)fj) : 0.0;
+    fp = in ? 1.0 : 0.0;
+  } else {
+    double fx = floor(xs), fy = floor(ys);
+    double t = xs - fx, s = ys - fy;
+    int n = INTERP == DFR_BILINEAR ? 2 : 4;
+    int64_t i0 = (int64_t)fx - (INTERP == DFR_BICUBIC ? 1 : 0);
+    int64_t j0 = (int64_t)fy - (INTERP == DFR_BICUBIC ? 1 : 0);
+    double wx[4], wy[4];
+    if constexpr (INTERP == DFR_BILINEAR) {
+      wx[0] = 1.0 - t; wx[1] = t; wy[0] = 1.0 - s; wy[1] = s;
+      wx[2] = wx[3] = wy[2] = wy[3] = 0.0;
+    } else {
+      double u = 1.0 - t, v = 1.0 - s;
+      wx[0] = a * t * u * u;
+      wx[1] = fma(fma(a + 2.0, t, -(a + 3.0)), t * t, 1.0);
+      wx[2] = fma(fma(a + 2.0, u, -(a + 3.0)), u * u, 1.0);
+      wx[3] = a * t * t * u;
+      wy[0] = a * s * v * v;
+      wy[1] = fma(fma(a + 2.0, s, -(a + 3.0)), s * s, 1.0);
+      wy[2] = fma(fma(a + 2.0, v, -(a + 3.0)), v * v, 1.0);
+      wy[3] = a * s * s * v;
+    }
+    double S = 0.0, Fx = 0.0, Fy = 0.0;
+    bool all_in = true;
+    for (int k = 0; k < n; ++k) {
+      bool ix = i0 + k >= 0 && i0 + k < W, iy = j0 + k >= 0 && j0 + k < H;
+      all_in = all_in && ix && iy;
+      Fx += ix ? wx[k] : 0.0;
+      Fy += iy ? wy[k] : 0.0;
+    }
+    for (int l = 0; l < n; ++l) {
+      if (j0 + l < 0 || j0 + l >= H) continue;
+      double row = 0.0;
+      for (int k = 0; k < n; ++k)
+        if (i0 + k >= 0 && i0 + k < W) row = fma(wx[k], val(i0 + k, j0 + l), row);
+      S = fma(wy[l], row, S);
+    }
+    double F = all_in ? 1.0 : Fx * Fy;
+    out = all_in ? S : (F > 0.0 ? S / F : 0.0);
+    fp = F > 0.0 ? F : 0.0;
+  }
+}
+
+// Paper section 3.2 literally (trigonometric two-stage form, FP64), with
+// the arcsines evaluated as atan2 of the same unit vector.
+__device__ __forceinline__ bool position_trig(const FramePlan &P, const TrigPlan &T, double x,
+                                              double y, double &xs, double &ys) {
+  const double R0 = 57.295779513082320876798;  // 180 / pi
+  double u = x - P.tcr[0], v = y - P.tcr[1];
+  if (P.t_order > 0) {
+    double du = sip_f64(P.tA, P.t_order, u, v);
+    double dv = sip_f64(P.tB, P.t_order, u, v);
+    u += du;
+    v += dv;
+  }
+  double up = T.tcd[0] * u + T.tcd[1] * v;
+  double vp = T.tcd[2] * u + T.tcd[3] * v;
+  double r = hypot(up, vp);
+  double phi = atan2(-up, vp);
+  double theta = atan2(R0, r);
+  double st, ct, sp, cp, sd0, cd0;
+  sincos(theta, &st, &ct);
+  sincos(phi, &sp, &cp);
+  sincos(T.tcrval[1], &sd0, &cd0);
+  double Z = st * sd0 + ct * cd0 * cp;
+  double X = -ct * sp;
+  double Y = st * cd0 - ct * sd0 * cp;
+  double dec = atan2(Z, hypot(X, Y));
+  double ra = T.tcrval[0] + atan2(X, Y);
+  // to the source plane
+  double sde, cde, sdr, cdr, ss0, cs0;
+  sincos(dec, &sde, &cde);
+  sincos(ra - T.scrval[0], &sdr, &cdr);
+  sincos(T.scrval[1], &ss0, &cs0);
+  double X2 = -cde * sdr;
+  double Y2 = sde * cs0 - cde * ss0 * cdr;
+  double Z2 = sde * ss0 + cde * cs0 * cdr;
+  if (!(Z2 > 0.0)) return false;
+  double phi2 = atan2(X2, Y2);
+  double theta2 = atan2(Z2, hypot(X2, Y2));
+  double st2, ct2, sp2, cp2;
+  sincos(theta2, &st2, &ct2);
+  sincos(phi2, &sp2, &cp2);
+  double r2 = R0 * ct2 / st2;
+  double xp = -r2 * sp2, yp = r2 * cp2;
+  double U = T.scdi[0] * xp + T.scdi[1] * yp;
+  double V = T.scdi[2] * xp + T.scdi[3] * yp;
+  if (P.s_order > 0) {
+    double dU = sip_f64(P.sA, P.s_order, U, V);
+    double dV = sip_f64(P.sB, P.s_order, U, V);
+    U += dU;
+    V += dV;
+  }
+  xs = U + P.scr[0];
+  ys = V + P.scr[1];
+  return isfinite(xs) && isfinite(ys);
+}
+
+template <int INTERP, bool TRIG>
+__global__ __launch_bounds__(kThreads) void reproject_f64(FramePlan P, TrigPlan T, TileGeom G) {
+  const int64_t n = (int64_t)G.out_h * G.out_w;
+  const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
+  for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * kThreads) {
+    const int y = (int)(idx / G.out_w), x = (int)(idx - (int64_t)y * G.out_w);
+    double xs = 0.0, ys = 0.0;
+    bool ok = TRIG ? position_trig(P, T, x, y, xs, ys) : position_f64(P, x, y, xs, ys);
+    ok = ok && fabs(xs) < 4.0e15 && fabs(ys) < 4.0e15;
+    double o = 0.0, f = 0.0;
+    if (ok && P.src_h > 0 && P.src_w > 0) interp_f64<INTERP>(P, xs, ys, (double)G.cubic_a, o, f);
+    bool cov = f > 0.0;
+    P.out[idx] = cov ? (float)o : miss;
+    if (P.fp) P.fp[idx] = cov ? (float)f : 0.0f;
+    if (G.debug) {
+      double2 d;
+      d.x = ok ? xs : __builtin_nan("");
+      d.y = ok ? ys : __builtin_nan("");
+      reinterpret_cast<double2 *>(G.debug)[idx] = d;
+    }
+  }
+}
+
+hipError_t launch_forward_f64(const FramePlan &P, const TrigPlan &T, const TileGeom &G,
+                              int interp, bool trig, hipStream_t stream) {
+  int64_t n = (int64_t)G.out_h * G.out_w;
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + kThreads - 1) / kThreads;
+  if (blocks > 65536 * 8) blocks = 65536 * 8;
+  void (*k)(FramePlan, TrigPlan, TileGeom);
+  if (trig) {
+    k = interp == DFR_NEAREST ? reproject_f64<DFR_NEAREST, true>
+        : interp == DFR_BILINEAR ? reproject_f64<DFR_BILINEAR, true>
+                                 : reproject_f64<DFR_BICUBIC, true>;
+  } else {
+    k = interp == DFR_NEAREST ? reproject_f64<DFR_NEAREST, false>
+        : interp == DFR_BILINEAR ? reproject_f64<DFR_BILINEAR, false>
+                                 : reproject_f64<DFR_BICUBIC, false>;
+  }
+  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kThreads), 0, stream, P, T, G);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void zero_f32_kernel(float *p, int64_t rows, int64_t cols, int64_t pitch) {
+  const int64_t n = rows * cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = i / cols;
+    p[r * pitch + (i - r * cols)] = 0.0f;
+  }
+}
+
+__global__ void zero_i32_kernel(int *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+const void *zero_i32_kernel_ptr() { return reinterpret_cast<const void *>(zero_i32_kernel); }
+
+hipError_t launch_zero_f32(float *p, int64_t rows, int64_t cols, int64_t pitch,
+                           hipStream_t stream) {
+  int64_t n = rows * cols;
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, rows,
+                     cols, pitch);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int *p, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace dfr

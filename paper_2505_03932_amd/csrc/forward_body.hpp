@@ -1,0 +1,422 @@
+// Reprojection of one output tile (paper section 3.1: source positions by
+// the two stages of section 3.2, interpolation, footprint normalisation).
+//
+// A tile is (kRun << txt_log2) x ((kThreads >> txt_log2) * NP) output
+// pixels.  Thread (tx, ty) owns NP runs of kRun consecutive pixels in rows
+// ty, ty + RP, ..., so every wave store covers contiguous row segments.
+//
+// Phases (shared by the forward and backward kernels)
+//   1. anchors: lanes 0..nA-1 of wave 0 evaluate the map in FP64 at the
+//      16x16-cell anchors the tile covers (<= 16) -> LDS;
+//   2. positions: every pixel's source position from FP32 offsets to its
+//      cell's anchor (Horner SIP in registers); nearest lanes within 1e-4 px
+//      of a rounding tie are recomputed entirely in FP64;
+//   3. exact bounding box of every in-image tap (wave min/max reductions,
+//      then LDS atomics across the 4 waves): the halo is exactly what the
+//      local Jacobian of the map needs;
+//   4. the box is staged in LDS with coalesced row loads (global gathers if
+//      it exceeds the LDS budget);
+//   5. forward: gather, footprint, normalisation and row stores.
+#pragma once
+
+#include "common.hpp"
+
+namespace dfr {
+
+constexpr int kRtOrder = -1;  // SORD value meaning "order read at run time"
+
+template <int SORD>
+__device__ __forceinline__ float sip_src(const float *__restrict__ c, int n, float x, float y) {
+  if constexpr (SORD == kRtOrder) {
+    return sip_f32_rt(c, n, x, y);
+  } else {
+    return sip_f32<SORD>(c, x, y);
+  }
+}
+
+// Offsets of one pixel from its anchor, in FP32.
+struct PixelGeom {
+  float du, dv;   // SIP-corrected target offset from the anchor
+  float r;        // 1 / (1 + k.d): ratio w_anchor / w_pixel
+  float dU, dV;   // source intermediate offset from the anchor
+  float us, vs;   // source intermediate / S_s (SIP arguments)
+};
+
+// FP32 source position of the pixel at offset (dx, dy) from its anchor,
+// relative to (A.bx, A.by).  Returns false for directions on or behind the
+// source tangent plane.
+template <int SORD>
+__device__ __forceinline__ bool pixel_position(const FramePlan &P, const Anchor &A, float tinv,
+                                               float sinv, float dx, float dy, float &rx,
+                                               float &ry, PixelGeom *geom = nullptr) {
+  float du = dx, dv = dy;
+  if (P.t_order > 0) {
+    float us = fmaf(dx, tinv, A.tus), vs = fmaf(dy, tinv, A.tvs);
+    du = dx + (sip_f32_rt(P.ftA, P.t_order, us, vs) - A.ta0);
+    dv = dy + (sip_f32_rt(P.ftB, P.t_order, us, vs) - A.tb0);
+  }
+  float den = fmaf(A.k1, du, fmaf(A.k2, dv, 1.0f));
+  float nu = fmaf(A.g1, du, A.g2 * dv);
+  float nv = fmaf(A.f1, du, A.f2 * dv);
+  float r = __builtin_amdgcn_rcpf(den);
+  float dU = nu * r, dV = nv * r;
+  float us = fmaf(dU, sinv, A.u0s), vs = fmaf(dV, sinv, A.v0s);
+  float ax = sip_src<SORD>(P.fsA, P.s_order, us, vs);
+  float ay = sip_src<SORD>(P.fsB, P.s_order, us, vs);
+  rx = (A.c0x + dU) + ax;
+  ry = (A.c0y + dV) + ay;
+  if (geom) {
+    geom->du = du;
+    geom->dv = dv;
+    geom->r = r;
+    geom->dU = dU;
+    geom->dV = dV;
+    geom->us = us;
+    geom->vs = vs;
+  }
+  return (A.sgn * den > 0.0f) && (fabsf(rx) < 1.0e7f) && (fabsf(ry) < 1.0e7f);
+}
+
+// Interpolation of one pixel.  `fetch(i, j)` reads source pixel (i, j) for
+// in-image taps.
+template <int INTERP, typename Fetch>
+__device__ __forceinline__ void interpolate(int bx, int by, float rx, float ry, int W, int H,
+                                            float cubic_a, const Fetch &fetch, float &out,
+                                            float &fp) {
+  if constexpr (INTERP == DFR_NEAREST) {
+    int i = bx + (int)rintf(rx);
+    int j = by + (int)rintf(ry);
+    bool in = ((unsigned)i < (unsigned)W) && ((unsigned)j < (unsigned)H);
+    out = in ? fetch(i, j) : 0.0f;
+    fp = in ? 1.0f : 0.0f;
+  } else if constexpr (INTERP == DFR_BILINEAR) {
+    float fx = floorf(rx), fy = floorf(ry);
+    float t = rx - fx, s = ry - fy;
+    int i0 = bx + (int)fx, j0 = by + (int)fy;
+    bool ix0 = (unsigned)i0 < (unsigned)W, ix1 = (unsigned)(i0 + 1) < (unsigned)W;
+    bool iy0 = (unsigned)j0 < (unsigned)H, iy1 = (unsigned)(j0 + 1) < (unsigned)H;
+    float wx0 = ix0 ? 1.0f - t : 0.0f, wx1 = ix1 ? t : 0.0f;
+    float wy0 = iy0 ? 1.0f - s : 0.0f, wy1 = iy1 ? s : 0.0f;
+    float v00 = (ix0 && iy0) ? fetch(i0, j0) : 0.0f;
+    float v01 = (ix1 && iy0) ? fetch(i0 + 1, j0) : 0.0f;
+    float v10 = (ix0 && iy1) ? fetch(i0, j0 + 1) : 0.0f;
+    float v11 = (ix1 && iy1) ? fetch(i0 + 1, j0 + 1) : 0.0f;
+    float S = fmaf(wy0, fmaf(wx0, v00, wx1 * v01), wy1 * fmaf(wx0, v10, wx1 * v11));
+    bool all_in = ix0 && ix1 && iy0 && iy1;
+    float F = all_in ? 1.0f : (wx0 + wx1) * (wy0 + wy1);
+    out = all_in ? S : (F > 0.0f ? S * __builtin_amdgcn_rcpf(F) : 0.0f);
+    fp = F > 0.0f ? F : 0.0f;
+  } else {
+    float fx = floorf(rx), fy = floorf(ry);
+    float t = rx - fx, s = ry - fy;
+    int i0 = bx + (int)fx - 1, j0 = by + (int)fy - 1;
+    float wx[4], wy[4];
+    keys_weights(t, cubic_a, wx);
+    keys_weights(s, cubic_a, wy);
+    bool inx[4], iny[4];
+    bool all_in = true;
+    float Fx = 0.0f, Fy = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      inx[k] = (unsigned)(i0 + k) < (unsigned)W;
+      iny[k] = (unsigned)(j0 + k) < (unsigned)H;
+      all_in = all_in && inx[k] && iny[k];
+      wx[k] = inx[k] ? wx[k] : 0.0f;
+      wy[k] = iny[k] ? wy[k] : 0.0f;
+      Fx += wx[k];
+      Fy += wy[k];
+    }
+    float S = 0.0f;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      float row = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float v = (inx[k] && iny[l]) ? fetch(i0 + k, j0 + l) : 0.0f;
+        row = fmaf(wx[k], v, row);
+      }
+      S = fmaf(wy[l], row, S);
+    }
+    float F = all_in ? 1.0f : Fx * Fy;
+    out = all_in ? S : (F > 0.0f ? S * __builtin_amdgcn_rcpf(F) : 0.0f);
+    fp = F > 0.0f ? F : 0.0f;
+  }
+}
+
+// LDS scratch of a tile kernel besides the dynamic source tile.
+struct TileShared {
+  Anchor anchor[kMaxAnchors];
+  int box[4];     // imin, imax, jmin, jmax of in-image taps
+  int touch;      // any anchor cell can reach the source
+  int item;       // batch: work item handed to this work-group
+};
+
+template <int INTERP>
+struct TapSupport {
+  static constexpr int lo = INTERP == DFR_BICUBIC ? 1 : 0;  // taps left/up of floor
+  static constexpr int hi = INTERP == DFR_NEAREST ? 0 : (INTERP == DFR_BILINEAR ? 1 : 2);
+};
+
+// Geometry of a tile and of the calling thread inside it.
+struct TileCtx {
+  int x0, y0;    // tile origin (output pixels)
+  int RP;        // rows per pass
+  int cx0, cy0;  // first anchor cell
+  int ncx;       // anchor cells per tile row
+  int ty;        // thread row in the tile
+  int xr;        // first output column of the thread's runs
+};
+
+// Phase 1.  Returns false when no pixel of the tile can reach the source
+// (and skipping is allowed): the caller then only writes "uncovered".
+template <int INTERP, int NP>
+__device__ __forceinline__ bool tile_anchors(const FramePlan &P, const TileGeom &G, int tile,
+                                             TileShared &sh, TileCtx &c) {
+  const int tid = threadIdx.x;
+  const int lg = G.txt_log2;
+  const int TW = kRun << lg;
+  c.RP = kThreads >> lg;
+  const int TH = c.RP * NP;
+  const int trow = tile / G.tiles_x;
+  c.x0 = (tile - trow * G.tiles_x) * TW;
+  c.y0 = trow * TH;
+  c.cx0 = c.x0 / kCell;
+  c.ncx = TW / kCell;
+  c.cy0 = c.y0 / kCell;
+  const int ncy = TH >= kCell ? TH / kCell : 1;
+  const int nA = c.ncx * ncy;
+  c.ty = tid >> lg;
+  c.xr = c.x0 + (tid & ((1 << lg) - 1)) * kRun;
+  if (tid < 64) {
+    int t = 0;
+    if (tid < nA) {
+      int cy = c.cy0 + tid / c.ncx, cx = c.cx0 + tid % c.ncx;
+      compute_anchor(P, cx * kCell, cy * kCell, TapSupport<INTERP>::hi, sh.anchor[tid]);
+      t = sh.anchor[tid].touch;
+    }
+    unsigned long long any = __ballot(t != 0);
+    if (tid == 0) {
+      sh.touch = any != 0ull;
+      sh.box[0] = 0x7fffffff;
+      sh.box[1] = -0x7fffffff;
+      sh.box[2] = 0x7fffffff;
+      sh.box[3] = -0x7fffffff;
+    }
+  }
+  __syncthreads();
+  return sh.touch || !G.allow_skip;
+}
+
+template <int NP>
+struct TilePos {
+  float rx[NP][kRun], ry[NP][kRun];
+  int abx[NP], aby[NP];  // anchor base of each run
+  int aidx[NP];          // anchor index of each run
+  unsigned valid;        // bit k*kRun+e: pixel (run k, element e) has a position
+  int bi0, bi1, bj0, bj1;
+  bool empty;            // no pixel of the tile has a tap inside the source
+};
+
+// Phases 2 and 3 (ends with a barrier; the box is then known to all).
+template <int INTERP, int SORD, int NP>
+__device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeom &G,
+                                               TileShared &sh, const TileCtx &c,
+                                               TilePos<NP> &T) {
+  constexpr int SLO = TapSupport<INTERP>::lo, SHI = TapSupport<INTERP>::hi;
+  const int W = P.src_w, Hs = P.src_h;
+  const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
+  int imin = 0x7fffffff, imax = -0x7fffffff, jmin = 0x7fffffff, jmax = -0x7fffffff;
+  T.valid = 0u;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int y = c.y0 + c.ty + k * c.RP;
+    const int a = ((y >> 4) - c.cy0) * c.ncx + ((c.xr >> 4) - c.cx0);
+    const Anchor &A = sh.anchor[a];
+    T.aidx[k] = a;
+    T.abx[k] = A.bx;
+    T.aby[k] = A.by;
+    const float dy = (float)(y & (kCell - 1));
+#pragma unroll
+    for (int e = 0; e < kRun; ++e) {
+      const int x = c.xr + e;
+      const float dx = (float)((c.xr & (kCell - 1)) + e);
+      float px, py;
+      bool ok = pixel_position<SORD>(P, A, tinv, sinv, dx, dy, px, py);
+      ok = ok && (y < G.out_h) && (x < G.out_w);
+      double dbx = 0.0, dby = 0.0;
+      bool exact = false;
+      if constexpr (INTERP == DFR_NEAREST) {
+        // a rounding decision within reach of the FP32 error: decide in FP64
+        float tx_ = px - floorf(px), ty_ = py - floorf(py);
+        if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
+          double xs, ys;
+          ok = position_f64(P, (double)x, (double)y, xs, ys) && fabs(xs - A.bx) < 1.0e7 &&
+               fabs(ys - A.by) < 1.0e7;
+          if (ok) {
+            px = (float)(rint(xs) - (double)A.bx);
+            py = (float)(rint(ys) - (double)A.by);
+            exact = true;
+            dbx = xs;
+            dby = ys;
+          }
+        }
+      }
+      T.rx[k][e] = px;
+      T.ry[k][e] = py;
+      if (G.debug && y < G.out_h && x < G.out_w) {
+        double2 d;
+        if (!ok) {
+          d.x = __builtin_nan("");
+          d.y = d.x;
+        } else if (exact) {
+          d.x = dbx;
+          d.y = dby;
+        } else {
+          d.x = (double)A.bx + (double)px;
+          d.y = (double)A.by + (double)py;
+        }
+        reinterpret_cast<double2 *>(G.debug)[(int64_t)y * G.out_w + x] = d;
+      }
+      if (ok) {
+        int ic, jc;
+        if constexpr (INTERP == DFR_NEAREST) {
+          ic = A.bx + (int)rintf(px);
+          jc = A.by + (int)rintf(py);
+        } else {
+          ic = A.bx + (int)floorf(px);
+          jc = A.by + (int)floorf(py);
+        }
+        int ilo = ic - SLO, ihi = ic + SHI, jlo = jc - SLO, jhi = jc + SHI;
+        if (ihi >= 0 && ilo < W && jhi >= 0 && jlo < Hs) {
+          imin = min(imin, max(ilo, 0));
+          imax = max(imax, min(ihi, W - 1));
+          jmin = min(jmin, max(jlo, 0));
+          jmax = max(jmax, min(jhi, Hs - 1));
+        }
+        T.valid |= 1u << (k * kRun + e);
+      }
+    }
+  }
+  imin = wave_min(imin);
+  imax = wave_max(imax);
+  jmin = wave_min(jmin);
+  jmax = wave_max(jmax);
+  if ((threadIdx.x & 63) == 0 && imin <= imax) {
+    atomicMin(&sh.box[0], imin);
+    atomicMax(&sh.box[1], imax);
+    atomicMin(&sh.box[2], jmin);
+    atomicMax(&sh.box[3], jmax);
+  }
+  __syncthreads();
+  T.bi0 = sh.box[0];
+  T.bi1 = sh.box[1];
+  T.bj0 = sh.box[2];
+  T.bj1 = sh.box[3];
+  T.empty = T.bi0 > T.bi1;
+  if (T.empty) T.valid = 0u;  // no tap inside the source: every pixel is uncovered
+}
+
+// Phase 4: copy the box [bi0, bi1] x [bj0, bj1] of the source into LDS (row
+// stride bw) with one wave per row and consecutive lanes on consecutive
+// columns.  The caller synchronises.
+__device__ __forceinline__ void stage_box(const FramePlan &P, int bi0, int bj0, int bw, int bh,
+                                          float *__restrict__ lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const float *__restrict__ s0 = P.src + (int64_t)bj0 * P.pitch + bi0;
+  for (int r = wave; r < bh; r += kThreads / 64) {
+    const float *__restrict__ sr = s0 + (int64_t)r * P.pitch;
+    float *__restrict__ lr = lds + r * bw;
+    for (int col = lane; col < bw; col += 64) lr[col] = sr[col];
+  }
+}
+
+__device__ __forceinline__ void store_run(float *__restrict__ base, int64_t off, int x, int out_w,
+                                          bool vec, const float v[kRun]) {
+  if (vec && x + kRun <= out_w) {
+    *reinterpret_cast<float4 *>(base + off) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < kRun; ++e)
+      if (x + e < out_w) base[off + e] = v[e];
+  }
+}
+
+__device__ __forceinline__ bool vector_stores_ok(const FramePlan &P, const TileGeom &G) {
+  return ((G.out_w & (kRun - 1)) == 0) && ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0) &&
+         (P.fp == nullptr || (reinterpret_cast<uintptr_t>(P.fp) & 15) == 0);
+}
+
+template <int INTERP, int SORD, int NP>
+__device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom &G, int tile,
+                                             float *__restrict__ lds, TileShared &sh) {
+  TileCtx c;
+  const bool work = tile_anchors<INTERP, NP>(P, G, tile, sh, c);
+  const bool vec = vector_stores_ok(P, G);
+  const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
+  if (!work) {
+    float zo[kRun], zf[kRun];
+#pragma unroll
+    for (int e = 0; e < kRun; ++e) {
+      zo[e] = miss;
+      zf[e] = 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      int y = c.y0 + c.ty + k * c.RP;
+      if (y >= G.out_h || c.xr >= G.out_w) continue;
+      int64_t off = (int64_t)y * G.out_w + c.xr;
+      store_run(P.out, off, c.xr, G.out_w, vec, zo);
+      if (P.fp) store_run(P.fp, off, c.xr, G.out_w, vec, zf);
+    }
+    return;
+  }
+  TilePos<NP> T;
+  tile_positions<INTERP, SORD, NP>(P, G, sh, c, T);
+  const int bw = T.empty ? 0 : T.bi1 - T.bi0 + 1;
+  const int bh = T.empty ? 0 : T.bj1 - T.bj0 + 1;
+  const bool use_lds = !T.empty && (int64_t)bw * bh <= (int64_t)G.lds_cap;
+  if (use_lds) stage_box(P, T.bi0, T.bj0, bw, bh, lds);
+  __syncthreads();
+
+  const int W = P.src_w, Hs = P.src_h;
+  const int bi0 = T.bi0, bi1 = T.bi1, bj0 = T.bj0, bj1 = T.bj1;
+  auto fetch_lds = [&](int i, int j) -> float {
+    i = min(max(i, bi0), bi1);
+    j = min(max(j, bj0), bj1);
+    return lds[(j - bj0) * bw + (i - bi0)];
+  };
+  auto fetch_glb = [&](int i, int j) -> float {
+    i = min(max(i, 0), W - 1);
+    j = min(max(j, 0), Hs - 1);
+    return P.src[(int64_t)j * P.pitch + i];
+  };
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int y = c.y0 + c.ty + k * c.RP;
+    if (y >= G.out_h || c.xr >= G.out_w) continue;
+    float o[kRun], f[kRun];
+#pragma unroll
+    for (int e = 0; e < kRun; ++e) {
+      o[e] = miss;
+      f[e] = 0.0f;
+      if (T.valid & (1u << (k * kRun + e))) {
+        float ov, fv;
+        if (use_lds)
+          interpolate<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs, G.cubic_a,
+                              fetch_lds, ov, fv);
+        else
+          interpolate<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs, G.cubic_a,
+                              fetch_glb, ov, fv);
+        if (fv > 0.0f) {
+          o[e] = ov;
+          f[e] = fv;
+        }
+      }
+    }
+    int64_t off = (int64_t)y * G.out_w + c.xr;
+    store_run(P.out, off, c.xr, G.out_w, vec, o);
+    if (P.fp) store_run(P.fp, off, c.xr, G.out_w, vec, f);
+  }
+}
+
+}  // namespace dfr

@@ -1,0 +1,72 @@
+// Host-side launch helpers shared by the translation units of libdfr.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace dfr {
+
+// Tile shapes: id 1..kTileCount.  id-1 = li*3 + ni with threads-per-row
+// 8 << li (tile width 32 << li px) and NP = 1 << ni rows per thread.
+constexpr int kTileCount = 12;
+constexpr int kDefaultTile = 5;  // 64 x 32
+
+struct TileShape {
+  int txt_log2;  // threads per tile row, log2
+  int np;        // rows per thread
+  int width, height;
+};
+
+inline bool tile_shape(int id, TileShape &s) {
+  if (id < 1 || id > kTileCount) return false;
+  int li = (id - 1) / 3, ni = (id - 1) % 3;
+  s.txt_log2 = 3 + li;
+  s.np = 1 << ni;
+  s.width = kRun << s.txt_log2;
+  s.height = (kThreads >> s.txt_log2) * s.np;
+  return true;
+}
+
+// Extra per-frame data the FP64 comparison forms need (trig form: the
+// explicit two-stage formulas of section 3.2).
+struct TrigPlan {
+  double tcd[4];     // target CD (deg/px)
+  double scdi[4];    // inverse of the source CD (px/deg)
+  double tcrval[2];  // target (RA, Dec) in radians
+  double scrval[2];  // source (RA, Dec) in radians
+};
+
+hipError_t launch_forward_f32(const FramePlan &P, const TileGeom &G, int interp, int np,
+                              hipStream_t stream);
+hipError_t launch_forward_f64(const FramePlan &P, const TrigPlan &T, const TileGeom &G,
+                              int interp, bool trig, hipStream_t stream);
+hipError_t launch_batch_f32(const FramePlan *plans_dev, int n_frames, int max_sord,
+                            const TileGeom &G, int interp, int np, int *counter,
+                            int grid, hipStream_t stream);
+const void *batch_kernel_ptr(int interp, int np, int sord);
+const void *zero_i32_kernel_ptr();
+int batch_blocks_per_cu(int interp, int np, int sord, int lds_bytes);
+// Number of per-tile FP64 partial sums the backward kernel produces for a
+// source SIP order (9 for H, 2 for CRPIX, AP and BP monomial sums).
+inline int backward_sums(int s_order) { return 11 + (s_order + 1) * (s_order + 2); }
+
+struct WcsJacobian {
+  double dh[54];  // dH_i / d theta_k at [k * 9 + i], theta = CRVAL1..2, CD1_1..CD2_2
+};
+
+hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, int np,
+                           const float *grad_out, float *grad_src, int64_t gsrc_pitch,
+                           double *partials, hipStream_t stream);
+hipError_t launch_backward_finish(const double *partials, int n_blocks, int n_sums,
+                                  double *totals, const WcsJacobian &jac, int s_order,
+                                  int ap_order, int bp_order, double s_scale, double *grad_wcs,
+                                  hipStream_t stream);
+hipError_t launch_zero_f32(float *p, int64_t rows, int64_t cols, int64_t pitch,
+                           hipStream_t stream);
+hipError_t launch_zero_i32(int *p, int64_t n, hipStream_t stream);
+hipError_t launch_sq_residual(const float *out, const float *ref, const float *mask, int64_t n,
+                              double *partials, int n_blocks, double *loss, float *grad_out,
+                              hipStream_t stream);
+
+}  // namespace dfr

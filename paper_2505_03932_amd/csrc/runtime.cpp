@@ -1,0 +1,323 @@
+// Host runtime: tile choice, the tuned-shape cache (optionally persisted as
+// JSON), launch geometry, per-device workspaces.
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "plan.hpp"
+
+namespace dfr {
+
+namespace {
+
+std::mutex g_tune_mutex;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+const char *cache_path() {
+  const char *p = std::getenv("DFR_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+// The cache file is a flat JSON object {"key": tile, ...}.
+void load_cache_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char *path = cache_path();
+  if (!path) return;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return;
+  std::string text;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+  std::fclose(f);
+  size_t i = 0;
+  while (true) {
+    size_t q0 = text.find('"', i);
+    if (q0 == std::string::npos) break;
+    size_t q1 = text.find('"', q0 + 1);
+    if (q1 == std::string::npos) break;
+    size_t colon = text.find(':', q1);
+    if (colon == std::string::npos) break;
+    int v = std::atoi(text.c_str() + colon + 1);
+    if (v >= 1 && v <= kTileCount) g_tune[text.substr(q0 + 1, q1 - q0 - 1)] = v;
+    i = colon + 1;
+  }
+}
+
+void save_cache_locked() {
+  const char *path = cache_path();
+  if (!path) return;
+  std::string tmp = std::string(path) + ".tmp";
+  FILE *f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return;
+  std::fprintf(f, "{");
+  bool first = true;
+  for (auto &kv : g_tune) {
+    std::fprintf(f, "%s\n  \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+    first = false;
+  }
+  std::fprintf(f, "\n}\n");
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
+int lds_need(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, int tile) {
+  TileShape s;
+  tile_shape(tile, s);
+  return estimate_lds_floats(P, out_h, out_w, s, interp);
+}
+
+}  // namespace
+
+std::string tune_key(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, bool batch) {
+  double mag = max_magnification(P, out_h, out_w);
+  int mb = mag > 0 ? (int)std::lround(std::log2(mag) * 2.0) : -99;
+  // rotation class from the map's Jacobian at the frame centre
+  double xs0, ys0, xs1, ys1;
+  int rb = 0;
+  double cx = 0.5 * (out_w - 1), cy = 0.5 * (out_h - 1);
+  if (position_f64(P, cx, cy, xs0, ys0) && position_f64(P, cx + 8.0, cy, xs1, ys1)) {
+    double ang = std::atan2(std::fabs(ys1 - ys0), std::fabs(xs1 - xs0)) * 180.0 / M_PI;
+    rb = (int)(ang / 10.0);
+  }
+  int sord = std::min(P.s_order, 6);
+  char key[128];
+  std::snprintf(key, sizeof(key), "%s:i%d:s%d:t%d:m%d:r%d", batch ? "batch" : "single", interp,
+                sord, P.t_order > 0 ? 1 : 0, mb, rb);
+  return key;
+}
+
+std::mutex &tune_mutex_for_batch() { return g_tune_mutex; }
+
+int tuned_tile(const std::string &key) {
+  load_cache_locked();
+  auto it = g_tune.find(key);
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+void tune_store(const std::string &key, int tile) {
+  std::lock_guard<std::mutex> lk(g_tune_mutex);
+  load_cache_locked();
+  g_tune[key] = tile;
+  save_cache_locked();
+}
+
+int choose_tile(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, int requested,
+                bool batch, int lds_factor) {
+  if (requested >= 1 && requested <= kTileCount) return requested;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    load_cache_locked();
+    if (!g_tune.empty()) {
+      auto it = g_tune.find(tune_key(P, out_h, out_w, interp, batch));
+      if (it != g_tune.end()) return it->second;
+    }
+  }
+  // heuristic: 64x32 when its source box fits the LDS budget, else the
+  // largest tile whose box does
+  if (lds_factor * lds_need(P, out_h, out_w, interp, kDefaultTile) <= kLdsMaxFloats)
+    return kDefaultTile;
+  const int order[] = {4, 8, 1, 7, 10};
+  for (int t : order)
+    if (lds_factor * lds_need(P, out_h, out_w, interp, t) <= kLdsMaxFloats) return t;
+  return 7;
+}
+
+void make_geom(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, int tile,
+               const dfr_options &o, TileGeom &G, TileShape &ts, int lds_factor) {
+  tile_shape(tile, ts);
+  std::memset(&G, 0, sizeof(G));
+  G.out_h = out_h;
+  G.out_w = out_w;
+  G.txt_log2 = ts.txt_log2;
+  G.tiles_x = (out_w + ts.width - 1) / ts.width;
+  int64_t ty = (out_h + ts.height - 1) / ts.height;
+  G.n_tiles = (int32_t)(G.tiles_x * ty);
+  int64_t need = (int64_t)lds_factor * estimate_lds_floats(P, out_h, out_w, ts, interp);
+  G.lds_cap = need <= kLdsMaxFloats ? (int32_t)need : 0;
+  G.cubic_a = (float)o.cubic_a;
+  G.nan_outside = o.nan_outside ? 1 : 0;
+  G.debug = o.debug_positions;
+  G.allow_skip = o.debug_positions ? 0 : 1;
+}
+
+// ------------------------------------------------------------ workspaces --
+
+namespace {
+std::mutex g_ws_mutex;
+std::map<std::pair<int, void *>, Workspace> g_ws;
+}  // namespace
+
+std::mutex &workspace_mutex() { return g_ws_mutex; }
+
+Workspace *workspace(hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  Workspace &w = g_ws[std::make_pair(dev, reinterpret_cast<void *>(stream))];
+  w.device = dev;
+  w.stream = stream;
+  return &w;
+}
+
+void *workspace_buffer(Workspace *w, size_t bytes) {
+  if (!w) return nullptr;
+  if (w->cap >= bytes && w->buf) return w->buf;
+  if (w->buf) {
+    // work already queued on this stream may still use the old buffer
+    if (hipStreamSynchronize(w->stream) != hipSuccess) return nullptr;
+    (void)hipFree(w->buf);
+    w->buf = nullptr;
+    w->cap = 0;
+  }
+  size_t cap = std::max<size_t>(bytes + bytes / 4, 1 << 20);
+  if (hipMalloc(&w->buf, cap) != hipSuccess) {
+    w->buf = nullptr;
+    return nullptr;
+  }
+  w->cap = cap;
+  return w->buf;
+}
+
+namespace {
+
+void destroy_graphs(Workspace &w) {
+  for (auto &g : w.graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  w.graphs.clear();
+}
+
+}  // namespace
+
+void release_workspaces() {
+  std::lock_guard<std::mutex> lk(g_ws_mutex);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  for (auto it = g_ws.begin(); it != g_ws.end();) {
+    if (it->first.first != dev) {
+      ++it;
+      continue;
+    }
+    Workspace &w = it->second;
+    (void)hipStreamSynchronize(w.stream);
+    destroy_graphs(w);
+    if (w.buf) (void)hipFree(w.buf);
+    if (w.host_plans) (void)hipHostFree(w.host_plans);
+    if (w.staged) (void)hipEventDestroy(w.staged);
+    it = g_ws.erase(it);
+  }
+}
+
+// ----------------------------------------------------------------- batch --
+
+dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int interp, int np,
+                     int max_sord, hipStream_t stream, bool graph) {
+  std::lock_guard<std::mutex> lk(g_ws_mutex);
+  Workspace *w = workspace(stream);
+  if (!w) return DFR_E_DEVICE;
+  const int n = (int)plans.size();
+  const size_t table = (size_t)n * sizeof(FramePlan);
+  char *dev = static_cast<char *>(workspace_buffer(w, 256 + table));
+  if (!dev) return DFR_E_NOMEM;
+  int *counter = reinterpret_cast<int *>(dev);
+  FramePlan *plans_dev = reinterpret_cast<FramePlan *>(dev + 256);
+  // the previous batch on this stream must have copied the staged table
+  if (w->staged_pending) {
+    if (hipEventSynchronize(w->staged) != hipSuccess) return DFR_E_DEVICE;
+    w->staged_pending = false;
+  }
+  if (w->host_cap < (size_t)n) {
+    if (w->host_plans) (void)hipHostFree(w->host_plans);
+    w->host_plans = nullptr;
+    w->host_cap = 0;
+    if (hipHostMalloc(reinterpret_cast<void **>(&w->host_plans), table, hipHostMallocDefault) !=
+        hipSuccess)
+      return DFR_E_NOMEM;
+    w->host_cap = n;
+  }
+  std::memcpy(w->host_plans, plans.data(), table);
+  int dev_id = 0, cus = 0;
+  if (hipGetDevice(&dev_id) != hipSuccess) return DFR_E_DEVICE;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess ||
+      cus < 1)
+    cus = 1;
+  const int lds_bytes = G.lds_cap * (int)sizeof(float);
+  const int grid = batch_blocks_per_cu(interp, np, max_sord, lds_bytes) * cus;
+  if (!graph) {
+    if (hipMemcpyAsync(plans_dev, w->host_plans, table, hipMemcpyHostToDevice, stream) !=
+        hipSuccess)
+      return DFR_E_DEVICE;
+    if (launch_batch_f32(plans_dev, n, max_sord, G, interp, np, counter, grid, stream) !=
+        hipSuccess)
+      return DFR_E_DEVICE;
+  } else {
+    BatchGraph *found = nullptr;
+    for (auto &g : w->graphs)
+      if (g.n == n && g.interp == interp && g.np == np && g.sord == max_sord && g.grid == grid &&
+          g.plans_dev == plans_dev && g.plans_host == w->host_plans &&
+          std::memcmp(&g.geom, &G, sizeof(G)) == 0)
+        found = &g;
+    if (!found) {
+      BatchGraph bg;
+      std::memset(&bg, 0, sizeof(bg));
+      bg.geom = G;
+      bg.n = n;
+      bg.interp = interp;
+      bg.np = np;
+      bg.sord = max_sord;
+      bg.grid = grid;
+      bg.plans_dev = plans_dev;
+      bg.plans_host = w->host_plans;
+      if (hipGraphCreate(&bg.graph, 0) != hipSuccess) return DFR_E_DEVICE;
+      hipGraphNode_t copy = nullptr, zero = nullptr, kern = nullptr;
+      bool ok = hipGraphAddMemcpyNode1D(&copy, bg.graph, nullptr, 0, plans_dev, w->host_plans,
+                                        table, hipMemcpyHostToDevice) == hipSuccess;
+      int64_t one = 1;
+      void *zargs[] = {&counter, &one};
+      hipKernelNodeParams zp;
+      std::memset(&zp, 0, sizeof(zp));
+      zp.func = const_cast<void *>(zero_i32_kernel_ptr());
+      zp.gridDim = dim3(1);
+      zp.blockDim = dim3(256);
+      zp.sharedMemBytes = 0;
+      zp.kernelParams = zargs;
+      ok = ok && hipGraphAddKernelNode(&zero, bg.graph, nullptr, 0, &zp) == hipSuccess;
+      TileGeom geom = G;
+      int nf = n;
+      void *kargs[] = {&plans_dev, &nf, &geom, &counter};
+      hipKernelNodeParams kp;
+      std::memset(&kp, 0, sizeof(kp));
+      kp.func = const_cast<void *>(batch_kernel_ptr(interp, np, max_sord));
+      kp.gridDim = dim3(grid);
+      kp.blockDim = dim3(kThreads);
+      kp.sharedMemBytes = lds_bytes;
+      kp.kernelParams = kargs;
+      hipGraphNode_t deps[2] = {copy, zero};
+      ok = ok && hipGraphAddKernelNode(&kern, bg.graph, deps, 2, &kp) == hipSuccess;
+      ok = ok && hipGraphInstantiate(&bg.exec, bg.graph, nullptr, nullptr, 0) == hipSuccess;
+      if (!ok) {
+        (void)hipGraphDestroy(bg.graph);
+        return DFR_E_DEVICE;
+      }
+      w->graphs.push_back(bg);
+      found = &w->graphs.back();
+    }
+    if (hipGraphLaunch(found->exec, stream) != hipSuccess) return DFR_E_DEVICE;
+  }
+  if (!w->staged && hipEventCreateWithFlags(&w->staged, hipEventDisableTiming) != hipSuccess)
+    return DFR_E_DEVICE;
+  if (hipEventRecord(w->staged, stream) != hipSuccess) return DFR_E_DEVICE;
+  w->staged_pending = true;
+  return DFR_OK;
+}
+
+}  // namespace dfr

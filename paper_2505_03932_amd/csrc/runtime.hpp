@@ -1,0 +1,70 @@
+// Host runtime of libdfr: tile choice and the tuned-shape cache, launch
+// geometry, per-(device, stream) workspaces and the graph-replayed batch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+
+namespace dfr {
+
+constexpr int kLdsMaxFloats = 16384;  // 64 KiB of LDS per work-group for staged source
+
+// Tile for a reprojection: `requested` if nonzero, else the tuned cache
+// entry for this kind of map, else a heuristic that fits the LDS budget.
+int choose_tile(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, int requested,
+                bool batch, int lds_factor = 1);
+
+// Key under which tuned tiles are cached: kind, interpolation, SIP order and
+// coarse classes of the map's magnification and rotation.
+std::string tune_key(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, bool batch);
+void tune_store(const std::string &key, int tile);
+// Cached tile for `key`, 0 if none (caller holds tune_mutex_for_batch()).
+int tuned_tile(const std::string &key);
+std::mutex &tune_mutex_for_batch();
+
+// lds_factor: copies of the source box a kernel keeps (backward: 2).
+void make_geom(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, int tile,
+               const dfr_options &o, TileGeom &G, TileShape &ts, int lds_factor = 1);
+
+// Scratch owned by the library for one (device, stream): device memory for
+// partial sums, the batch frame table and its counter, pinned staging for
+// the frame table, and the instantiated batch graphs.  Work on one stream is
+// ordered, so reusing the buffers call after call is safe; every function
+// here must be called with workspace_mutex() held.
+struct BatchGraph {
+  TileGeom geom;
+  int n, interp, np, sord, grid;
+  void *plans_dev;
+  void *plans_host;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+struct Workspace {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  void *buf = nullptr;  // device scratch
+  size_t cap = 0;
+  FramePlan *host_plans = nullptr;  // pinned staging of the batch frame table
+  size_t host_cap = 0;              // in frames
+  hipEvent_t staged = nullptr;      // recorded after the last batch that read host_plans
+  bool staged_pending = false;
+  std::vector<BatchGraph> graphs;
+};
+
+std::mutex &workspace_mutex();
+Workspace *workspace(hipStream_t stream);
+void *workspace_buffer(Workspace *w, size_t bytes);
+void release_workspaces();
+
+// Reproject a batch in one persistent launch; `graph` replays a cached HIP
+// graph (frame-table copy, counter reset, persistent kernel).
+dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int interp, int np,
+                     int max_sord, hipStream_t stream, bool graph);
+
+}  // namespace dfr
