@@ -79,7 +79,7 @@ struct TileGeom {
 };
 
 // Per-cell quantities from the FP64 anchor evaluation (kept in LDS).
-struct Anchor {
+struct alignas(16) Anchor {
   float g1, g2, f1, f2, k1, k2;  // dU = (g.d)/(1 + k.d), dV = (f.d)/(1 + k.d)
   float u0s, v0s;                // (U0, V0) / S_s
   float c0x, c0y;                // X0 - bx, Y0 - by in [0, 1)
@@ -90,7 +90,7 @@ struct Anchor {
   float tu0, tv0;                // SIP-corrected target offset of the anchor (u, v)
   int32_t bx, by;                // integer parts of the anchor source position
   int32_t touch;                 // 0 when no pixel of the cell can reach the source
-  int32_t pad_;
+  int32_t ok;                    // every pixel of the cell has a valid, finite position
 };
 
 // ------------------------------------------------------ SIP polynomials --
@@ -150,6 +150,31 @@ __device__ __forceinline__ void sip_f32_grad(const float *__restrict__ c, float 
         f = fmaf(f, x, in);
         fy = fmaf(fy, x, din);
       }
+    }
+  }
+}
+
+// Value and partial derivatives with a run-time order.
+__device__ __forceinline__ void sip_f32_grad_rt(const float *__restrict__ c, int n, float x,
+                                                float y, float &f, float &fx, float &fy) {
+  f = 0.0f;
+  fx = 0.0f;
+  fy = 0.0f;
+  if (n <= 0) return;
+  for (int p = n; p >= 0; --p) {
+    float in = c[tri9(p, n - p)];
+    float din = 0.0f;
+    for (int q = n - p - 1; q >= 0; --q) {
+      din = fmaf(din, y, in);
+      in = fmaf(in, y, c[tri9(p, q)]);
+    }
+    if (p == n) {
+      f = in;
+      fy = din;
+    } else {
+      fx = fmaf(fx, x, f);
+      f = fmaf(f, x, in);
+      fy = fmaf(fy, x, din);
     }
   }
 }
@@ -243,6 +268,7 @@ __device__ __forceinline__ void compute_anchor(const FramePlan &P, int xa, int y
     A.c0y = 0.0f;
     A.sgn = 0.0f;  // sgn * den > 0 never holds: every pixel is invalid
     A.touch = 0;
+    A.ok = 0;
     return;
   }
   double fx = floor(X0), fy = floor(Y0);
@@ -254,17 +280,23 @@ __device__ __forceinline__ void compute_anchor(const FramePlan &P, int xa, int y
   // 15 px per axis; its image lies within (|g1|+|g2|, |f1|+|f2|) * 15 of the
   // anchor's, grown by the projective denominator and by the source SIP
   // (bounded by a generous factor 2), plus the tap support and 8 px.
-  double xs = X0, ys = Y0;
-  if (P.s_order > 0) {
-    xs += sip_f64(P.sA, P.s_order, U0, V0);
-    ys += sip_f64(P.sB, P.s_order, U0, V0);
-  }
+  // The SIP displacement and its slope at the anchor (only roughly needed):
+  // with slope L, the cell's source image lies within (1 + 2L) times the
+  // affine reach of the anchor while the slope stays below 1/2 over it.
+  float fa, fau, fav, fb, fbu, fbv;
+  sip_f32_grad_rt(P.fsA, P.s_order, A.u0s, A.v0s, fa, fau, fav);
+  sip_f32_grad_rt(P.fsB, P.s_order, A.u0s, A.v0s, fb, fbu, fbv);
+  double L = (fabs((double)fau) + fabs((double)fav) + fabs((double)fbu) + fabs((double)fbv)) *
+             P.s_inv_scale;
+  double xs = X0 + (double)fa, ys = Y0 + (double)fb;
   double kk = (fabs(H[6]) + fabs(H[7])) * fabs(iw) * 2.0 * kCell;
-  double mx = 2.0 * kCell * (fabs((double)A.g1) + fabs((double)A.g2)) + 8.0 + support;
-  double my = 2.0 * kCell * (fabs((double)A.f1) + fabs((double)A.f2)) + 8.0 + support;
+  // w > 0 at the anchor and |k . d| < 1/4 over the cell: w > 0 at every pixel
+  A.ok = (w > 0.0 && kk < 0.5) ? 1 : 0;
+  double mx = 2.0 * kCell * (fabs((double)A.g1) + fabs((double)A.g2)) * (1.0 + 2.0 * L) + 8.0 + support;
+  double my = 2.0 * kCell * (fabs((double)A.f1) + fabs((double)A.f2)) * (1.0 + 2.0 * L) + 8.0 + support;
   bool outside = (xs < -mx) || (xs > (double)(P.src_w - 1) + mx) || (ys < -my) ||
                  (ys > (double)(P.src_h - 1) + my);
-  A.touch = (w > 0.0 && kk < 0.5 && outside && P.t_order == 0) ? 0 : 1;
+  A.touch = (w > 0.0 && kk < 0.5 && L < 0.25 && outside && P.t_order == 0) ? 0 : 1;
   if (P.src_h <= 0 || P.src_w <= 0) A.touch = 0;
 }
 

@@ -146,9 +146,11 @@ __device__ __forceinline__ void interpolate(int bx, int by, float rx, float ry, 
 // LDS scratch of a tile kernel besides the dynamic source tile.
 struct TileShared {
   Anchor anchor[kMaxAnchors];
-  int box[4];     // imin, imax, jmin, jmax of in-image taps
+  int box[4];     // imin, imax, jmin, jmax of the source box
   int touch;      // any anchor cell can reach the source
   int item;       // batch: work item handed to this work-group
+  int cells_ok;   // forward: every anchor cell has valid positions throughout
+  int box_ok;     // forward: the 9 box samples are all valid
 };
 
 template <int INTERP>
@@ -346,14 +348,231 @@ __device__ __forceinline__ bool vector_stores_ok(const FramePlan &P, const TileG
          (P.fp == nullptr || (reinterpret_cast<uintptr_t>(P.fp) & 15) == 0);
 }
 
+// -------------------------------------------------------------- forward --
+//
+// The forward tile runs a different schedule from the one above, built so
+// that the source staging overlaps the position arithmetic:
+//   1. wave 0: the FP64 anchors of the tile's cells; wave 1, at the same
+//      time: FP64 source positions at 9 points of the tile (corners, edge
+//      midpoints, centre) giving the tile's source box, grown by the tap
+//      support and 2 px;
+//   2. the box is staged into LDS with asynchronous global->LDS DMA loads
+//      (gfx950 global_load_lds_dword), row by row;
+//   3. meanwhile every pixel's FP32 position is computed;
+//   4. wait for the DMA, then gather.  A tile whose box lies inside the
+//      source, whose cells all have valid positions and which lies inside the
+//      output takes an unmasked path (footprint exactly 1); every pixel is
+//      still checked against the box and a wave with any pixel outside it
+//      takes the general (masked, global-fallback) path, so the box is only
+//      a performance hint.
+
+// Values of one pixel's in-image taps combined the same way on every path
+// (so all paths agree bit for bit where all taps are inside the source).
+template <int INTERP>
+struct Taps;
+
+template <>
+struct Taps<DFR_BILINEAR> {
+  template <typename Fetch>
+  __device__ static __forceinline__ float interior(int i0, int j0, float t, float s, const Fetch &f) {
+    float v00 = f(i0, j0), v01 = f(i0 + 1, j0), v10 = f(i0, j0 + 1), v11 = f(i0 + 1, j0 + 1);
+    float top = fmaf(t, v01 - v00, v00);
+    float bot = fmaf(t, v11 - v10, v10);
+    return fmaf(s, bot - top, top);
+  }
+};
+
+template <>
+struct Taps<DFR_BICUBIC> {
+  template <typename Fetch>
+  __device__ static __forceinline__ float interior(int i0, int j0, const float wx[4],
+                                                   const float wy[4], const Fetch &f) {
+    float S = 0.0f;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      float row = wx[0] * f(i0, j0 + l);
+      row = fmaf(wx[1], f(i0 + 1, j0 + l), row);
+      row = fmaf(wx[2], f(i0 + 2, j0 + l), row);
+      row = fmaf(wx[3], f(i0 + 3, j0 + l), row);
+      S = fmaf(wy[l], row, S);
+    }
+    return S;
+  }
+};
+
+// General interpolation: taps outside the source are dropped (zero padding)
+// and the value is normalised by the footprint; identical to the interior
+// formula where every tap is inside.  `fetch` receives source coordinates.
+template <int INTERP, typename Fetch>
+__device__ __forceinline__ void interp_general(int i0, int j0, float t, float s, int W, int H,
+                                               float a, const Fetch &fetch, float &out,
+                                               float &fp) {
+  if constexpr (INTERP == DFR_NEAREST) {
+    bool in = ((unsigned)i0 < (unsigned)W) && ((unsigned)j0 < (unsigned)H);
+    out = in ? fetch(i0, j0) : 0.0f;
+    fp = in ? 1.0f : 0.0f;
+  } else if constexpr (INTERP == DFR_BILINEAR) {
+    bool ix0 = (unsigned)i0 < (unsigned)W, ix1 = (unsigned)(i0 + 1) < (unsigned)W;
+    bool iy0 = (unsigned)j0 < (unsigned)H, iy1 = (unsigned)(j0 + 1) < (unsigned)H;
+    if (ix0 && ix1 && iy0 && iy1) {
+      out = Taps<DFR_BILINEAR>::interior(i0, j0, t, s, fetch);
+      fp = 1.0f;
+      return;
+    }
+    float wx0 = ix0 ? 1.0f - t : 0.0f, wx1 = ix1 ? t : 0.0f;
+    float wy0 = iy0 ? 1.0f - s : 0.0f, wy1 = iy1 ? s : 0.0f;
+    float v00 = (ix0 && iy0) ? fetch(i0, j0) : 0.0f;
+    float v01 = (ix1 && iy0) ? fetch(i0 + 1, j0) : 0.0f;
+    float v10 = (ix0 && iy1) ? fetch(i0, j0 + 1) : 0.0f;
+    float v11 = (ix1 && iy1) ? fetch(i0 + 1, j0 + 1) : 0.0f;
+    float S = fmaf(wy0, fmaf(wx0, v00, wx1 * v01), wy1 * fmaf(wx0, v10, wx1 * v11));
+    float F = (wx0 + wx1) * (wy0 + wy1);
+    out = F > 0.0f ? S * __builtin_amdgcn_rcpf(F) : 0.0f;
+    fp = F > 0.0f ? F : 0.0f;
+  } else {
+    float wx[4], wy[4];
+    keys_weights(t, a, wx);
+    keys_weights(s, a, wy);
+    bool inx[4], iny[4];
+    bool all_in = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      inx[k] = (unsigned)(i0 + k) < (unsigned)W;
+      iny[k] = (unsigned)(j0 + k) < (unsigned)H;
+      all_in = all_in && inx[k] && iny[k];
+    }
+    if (all_in) {
+      out = Taps<DFR_BICUBIC>::interior(i0, j0, wx, wy, fetch);
+      fp = 1.0f;
+      return;
+    }
+    float Fx = 0.0f, Fy = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      wx[k] = inx[k] ? wx[k] : 0.0f;
+      wy[k] = iny[k] ? wy[k] : 0.0f;
+      Fx += wx[k];
+      Fy += wy[k];
+    }
+    float S = 0.0f;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      float row = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float v = (inx[k] && iny[l]) ? fetch(i0 + k, j0 + l) : 0.0f;
+        row = fmaf(wx[k], v, row);
+      }
+      S = fmaf(wy[l], row, S);
+    }
+    float F = Fx * Fy;
+    out = F > 0.0f ? S * __builtin_amdgcn_rcpf(F) : 0.0f;
+    fp = F > 0.0f ? F : 0.0f;
+  }
+}
+
+// First tap and fractions of a position (relative to an integer base).
+template <int INTERP>
+__device__ __forceinline__ void tap_origin(float r, int base, int &i0, float &t) {
+  if constexpr (INTERP == DFR_NEAREST) {
+    i0 = base + (int)rintf(r);
+    t = 0.0f;
+  } else {
+    float f = floorf(r);
+    t = r - f;
+    i0 = base + (int)f - TapSupport<INTERP>::lo;
+  }
+}
+
+// Wave 1 of phase 1: FP64 positions at 9 points of the tile's rectangle
+// (clipped to the output), their bounding box grown by the tap support and
+// 2 px, and whether all 9 are valid.
+template <int INTERP>
+__device__ __forceinline__ void tile_box_samples(const FramePlan &P, const TileGeom &G, int x0,
+                                                 int y0, int TW, int TH, TileShared &sh) {
+  const int lane = threadIdx.x & 63;
+  const int xe = min(x0 + TW, G.out_w) - 1, ye = min(y0 + TH, G.out_h) - 1;
+  bool ok = true;
+  int imn = 0x3fffffff, imx = -0x3fffffff, jmn = 0x3fffffff, jmx = -0x3fffffff;
+  if (lane < 9) {
+    const int ix = lane % 3, iy = lane / 3;
+    const double px = ix == 0 ? x0 : (ix == 1 ? 0.5 * (x0 + xe) : (double)xe);
+    const double py = iy == 0 ? y0 : (iy == 1 ? 0.5 * (y0 + ye) : (double)ye);
+    double xs, ys;
+    ok = position_f64(P, px, py, xs, ys) && fabs(xs) < 1.0e9 && fabs(ys) < 1.0e9;
+    if (ok) {
+      imn = (int)floor(xs);
+      imx = imn;
+      jmn = (int)floor(ys);
+      jmx = jmn;
+    }
+  }
+  imn = wave_min(imn);
+  imx = wave_max(imx);
+  jmn = wave_min(jmn);
+  jmx = wave_max(jmx);
+  const unsigned long long bad = __ballot(!ok);
+  if (lane == 0) {
+    constexpr int lo = TapSupport<INTERP>::lo + 2, hi = TapSupport<INTERP>::hi + 2;
+    sh.box[0] = imn - lo;
+    sh.box[1] = imx + hi;
+    sh.box[2] = jmn - lo;
+    sh.box[3] = jmx + hi;
+    sh.box_ok = bad == 0ull;
+  }
+}
+
+// Stage rows [bj0, bj0+bh) x columns [bi0, bi0+bw) of the source into LDS
+// (row stride bw) with asynchronous DMA: one wave per row, 64 columns per
+// instruction, lanes past the row end masked off.
+__device__ __forceinline__ void dma_box(const FramePlan &P, int bi0, int bj0, int bw, int bh,
+                                        float *__restrict__ lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const float *__restrict__ s0 = P.src + (int64_t)bj0 * P.pitch + bi0;
+  for (int r = wave; r < bh; r += kThreads / 64) {
+    const float *sr = s0 + (int64_t)r * P.pitch;
+    for (int c0 = 0; c0 < bw; c0 += 64) {
+      if (c0 + lane < bw)
+        __builtin_amdgcn_global_load_lds(sr + c0 + lane, lds + r * bw + c0, 4, 0, 0);
+    }
+  }
+}
+
 template <int INTERP, int SORD, int NP>
 __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom &G, int tile,
                                              float *__restrict__ lds, TileShared &sh) {
-  TileCtx c;
-  const bool work = tile_anchors<INTERP, NP>(P, G, tile, sh, c);
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int lg = G.txt_log2;
+  const int TW = kRun << lg, RP = kThreads >> lg, TH = RP * NP;
+  const int trow = tile / G.tiles_x;
+  const int x0 = (tile - trow * G.tiles_x) * TW, y0 = trow * TH;
+  const int cx0 = x0 / kCell, ncx = TW / kCell, cy0 = y0 / kCell;
+  const int nA = ncx * (TH >= kCell ? TH / kCell : 1);
+  const int ty = tid >> lg, xr = x0 + (tid & ((1 << lg) - 1)) * kRun;
+  const int W = P.src_w, Hs = P.src_h;
+
+  // ---- 1. anchors (wave 0) and the source box (wave 1), FP64
+  if (wave == 0) {
+    int t = 0, okc = 1;
+    if (tid < nA) {
+      int cy = cy0 + tid / ncx, cx = cx0 + tid % ncx;
+      compute_anchor(P, cx * kCell, cy * kCell, TapSupport<INTERP>::hi, sh.anchor[tid]);
+      t = sh.anchor[tid].touch;
+      okc = sh.anchor[tid].ok;
+    }
+    const unsigned long long any = __ballot(t != 0), bad = __ballot(okc == 0);
+    if (tid == 0) {
+      sh.touch = any != 0ull;
+      sh.cells_ok = bad == 0ull;
+    }
+  } else if (wave == 1) {
+    tile_box_samples<INTERP>(P, G, x0, y0, TW, TH, sh);
+  }
+  __syncthreads();
+
   const bool vec = vector_stores_ok(P, G);
   const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
-  if (!work) {
+  if (!sh.touch && G.allow_skip) {
     float zo[kRun], zf[kRun];
 #pragma unroll
     for (int e = 0; e < kRun; ++e) {
@@ -362,60 +581,170 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
     }
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-      int y = c.y0 + c.ty + k * c.RP;
-      if (y >= G.out_h || c.xr >= G.out_w) continue;
-      int64_t off = (int64_t)y * G.out_w + c.xr;
-      store_run(P.out, off, c.xr, G.out_w, vec, zo);
-      if (P.fp) store_run(P.fp, off, c.xr, G.out_w, vec, zf);
+      int y = y0 + ty + k * RP;
+      if (y >= G.out_h || xr >= G.out_w) continue;
+      int64_t off = (int64_t)y * G.out_w + xr;
+      store_run(P.out, off, xr, G.out_w, vec, zo);
+      if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, zf);
     }
     return;
   }
-  TilePos<NP> T;
-  tile_positions<INTERP, SORD, NP>(P, G, sh, c, T);
-  const int bw = T.empty ? 0 : T.bi1 - T.bi0 + 1;
-  const int bh = T.empty ? 0 : T.bj1 - T.bj0 + 1;
-  const bool use_lds = !T.empty && (int64_t)bw * bh <= (int64_t)G.lds_cap;
-  if (use_lds) stage_box(P, T.bi0, T.bj0, bw, bh, lds);
-  __syncthreads();
 
-  const int W = P.src_w, Hs = P.src_h;
-  const int bi0 = T.bi0, bi1 = T.bi1, bj0 = T.bj0, bj1 = T.bj1;
-  auto fetch_lds = [&](int i, int j) -> float {
-    i = min(max(i, bi0), bi1);
-    j = min(max(j, bj0), bj1);
-    return lds[(j - bj0) * bw + (i - bi0)];
-  };
-  auto fetch_glb = [&](int i, int j) -> float {
-    i = min(max(i, 0), W - 1);
-    j = min(max(j, 0), Hs - 1);
-    return P.src[(int64_t)j * P.pitch + i];
-  };
+  // ---- 2. stage the box (asynchronous)
+  const int bu0 = sh.box[0], bu1 = sh.box[1], bu2 = sh.box[2], bu3 = sh.box[3];
+  const int bi0 = max(bu0, 0), bi1 = min(bu1, W - 1), bj0 = max(bu2, 0), bj1 = min(bu3, Hs - 1);
+  const bool box_ok = sh.box_ok && bi0 <= bi1 && bj0 <= bj1;
+  const int bw = box_ok ? bi1 - bi0 + 1 : 0, bh = box_ok ? bj1 - bj0 + 1 : 0;
+  const bool use_lds = box_ok && (int64_t)bw * bh <= (int64_t)G.lds_cap;
+  const bool interior = use_lds && sh.cells_ok && P.t_order == 0 && bu0 == bi0 && bu1 == bi1 &&
+                        bu2 == bj0 && bu3 == bj1 && x0 + TW <= G.out_w && y0 + TH <= G.out_h;
+  if (use_lds) dma_box(P, bi0, bj0, bw, bh, lds);
+
+  // ---- 3. positions (FP32 offsets from the anchors)
+  const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
+  float rx[NP][kRun], ry[NP][kRun];
+  int abx[NP], aby[NP];
+  unsigned valid = 0u;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    const int y = c.y0 + c.ty + k * c.RP;
-    if (y >= G.out_h || c.xr >= G.out_w) continue;
+    const int y = y0 + ty + k * RP;
+    const Anchor &A = sh.anchor[((y >> 4) - cy0) * ncx + ((xr >> 4) - cx0)];
+    abx[k] = A.bx;
+    aby[k] = A.by;
+    const float dy = (float)(y & (kCell - 1));
+#pragma unroll
+    for (int e = 0; e < kRun; ++e) {
+      const int x = xr + e;
+      float px, py;
+      bool ok = pixel_position<SORD>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy, px,
+                                     py);
+      ok = ok && (y < G.out_h) && (x < G.out_w);
+      double dbx = 0.0, dby = 0.0;
+      bool exact = false;
+      if constexpr (INTERP == DFR_NEAREST) {
+        // a rounding decision within reach of the FP32 error: decide in FP64
+        float tx_ = px - floorf(px), ty_ = py - floorf(py);
+        if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
+          double xs, ys;
+          ok = position_f64(P, (double)x, (double)y, xs, ys) && fabs(xs - A.bx) < 1.0e7 &&
+               fabs(ys - A.by) < 1.0e7;
+          if (ok) {
+            px = (float)(rint(xs) - (double)A.bx);
+            py = (float)(rint(ys) - (double)A.by);
+            exact = true;
+            dbx = xs;
+            dby = ys;
+          }
+        }
+      }
+      rx[k][e] = px;
+      ry[k][e] = py;
+      if (G.debug && y < G.out_h && x < G.out_w) {
+        double2 d;
+        if (!ok) {
+          d.x = __builtin_nan("");
+          d.y = d.x;
+        } else if (exact) {
+          d.x = dbx;
+          d.y = dby;
+        } else {
+          d.x = (double)A.bx + (double)px;
+          d.y = (double)A.by + (double)py;
+        }
+        reinterpret_cast<double2 *>(G.debug)[(int64_t)y * G.out_w + x] = d;
+      }
+      if (ok) valid |= 1u << (k * kRun + e);
+    }
+  }
+
+  // ---- 4. gather
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  constexpr int SPAN = TapSupport<INTERP>::lo + TapSupport<INTERP>::hi;
+  // every tap of every pixel inside the staged box?
+  bool fast = interior;
+  if (fast) {
+    bool inside = true;
+#pragma unroll
+    for (int k = 0; k < NP; ++k)
+#pragma unroll
+      for (int e = 0; e < kRun; ++e) {
+        int i0, j0;
+        float t_, s_;
+        tap_origin<INTERP>(rx[k][e], abx[k] - bi0, i0, t_);
+        tap_origin<INTERP>(ry[k][e], aby[k] - bj0, j0, s_);
+        inside = inside && ((unsigned)i0 <= (unsigned)(bw - 1 - SPAN)) &&
+                 ((unsigned)j0 <= (unsigned)(bh - 1 - SPAN));
+      }
+    fast = __ballot(!inside) == 0ull;
+  }
+  const float a = G.cubic_a;
+  if (fast) {
+    // box-relative tap coordinates: unmasked LDS reads, footprint exactly 1
+    auto fl = [&](int i, int j) -> float { return lds[__umul24(j, bw) + i]; };
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int y = y0 + ty + k * RP;
+      float o[kRun], f[kRun];
+#pragma unroll
+      for (int e = 0; e < kRun; ++e) {
+        int i0, j0;
+        float t_, s_;
+        tap_origin<INTERP>(rx[k][e], abx[k] - bi0, i0, t_);
+        tap_origin<INTERP>(ry[k][e], aby[k] - bj0, j0, s_);
+        if constexpr (INTERP == DFR_NEAREST) {
+          o[e] = fl(i0, j0);
+        } else if constexpr (INTERP == DFR_BILINEAR) {
+          o[e] = Taps<DFR_BILINEAR>::interior(i0, j0, t_, s_, fl);
+        } else {
+          float wx[4], wy[4];
+          keys_weights(t_, a, wx);
+          keys_weights(s_, a, wy);
+          o[e] = Taps<DFR_BICUBIC>::interior(i0, j0, wx, wy, fl);
+        }
+        f[e] = 1.0f;
+      }
+      const int64_t off = (int64_t)y * G.out_w + xr;
+      store_run(P.out, off, xr, G.out_w, vec, o);
+      if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, f);
+    }
+    return;
+  }
+  // general path: source coordinates, zero padding, footprint normalisation;
+  // taps come from LDS when the pixel's taps are inside the staged box
+  auto fl = [&](int i, int j) -> float { return lds[__umul24(j - bj0, bw) + (i - bi0)]; };
+  auto fg = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int y = y0 + ty + k * RP;
+    if (y >= G.out_h || xr >= G.out_w) continue;
     float o[kRun], f[kRun];
 #pragma unroll
     for (int e = 0; e < kRun; ++e) {
       o[e] = miss;
       f[e] = 0.0f;
-      if (T.valid & (1u << (k * kRun + e))) {
+      if (valid & (1u << (k * kRun + e))) {
+        int i0, j0;
+        float t_, s_;
+        tap_origin<INTERP>(rx[k][e], abx[k], i0, t_);
+        tap_origin<INTERP>(ry[k][e], aby[k], j0, s_);
+        // the in-image part of the tap box must lie in the staged box
+        const bool in_lds = use_lds && max(i0, 0) >= bi0 && min(i0 + SPAN, W - 1) <= bi1 &&
+                            max(j0, 0) >= bj0 && min(j0 + SPAN, Hs - 1) <= bj1;
         float ov, fv;
-        if (use_lds)
-          interpolate<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs, G.cubic_a,
-                              fetch_lds, ov, fv);
+        if (in_lds)
+          interp_general<INTERP>(i0, j0, t_, s_, W, Hs, a, fl, ov, fv);
         else
-          interpolate<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs, G.cubic_a,
-                              fetch_glb, ov, fv);
+          interp_general<INTERP>(i0, j0, t_, s_, W, Hs, a, fg, ov, fv);
         if (fv > 0.0f) {
           o[e] = ov;
           f[e] = fv;
         }
       }
     }
-    int64_t off = (int64_t)y * G.out_w + c.xr;
-    store_run(P.out, off, c.xr, G.out_w, vec, o);
-    if (P.fp) store_run(P.fp, off, c.xr, G.out_w, vec, f);
+    const int64_t off = (int64_t)y * G.out_w + xr;
+    store_run(P.out, off, xr, G.out_w, vec, o);
+    if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, f);
   }
 }
 
