@@ -1,0 +1,154 @@
+"""Backward pass on the GPU: source-image adjoint and WCS-parameter gradient
+against the FP64 oracle gradient (which the CPU tests pin to central finite
+differences), the adjoint identity, the loss kernel and autograd."""
+import numpy as np
+import pytest
+import torch
+
+from synth import configs
+
+pytestmark = pytest.mark.gpu
+
+INTERPS = {0: "nearest", 1: "bilinear", 2: "bicubic"}
+
+
+@pytest.fixture(scope="module")
+def dfr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_03932_amd as d
+    return d
+
+
+def grad_case(size):
+    c = configs.grad(size=size)
+    return c, c.extra["src_wcs_true"]
+
+
+def interior_mask(orc, c, true_w):
+    _, _, pos = orc.reproject(c.src, true_w, c.tgt_wcs, c.out_shape, 2, want_pos=True)
+    h, w = c.src.shape
+    return ((pos[..., 0] >= 3) & (pos[..., 0] <= w - 4) & (pos[..., 1] >= 3) &
+            (pos[..., 1] <= h - 4))
+
+
+def _compare_wcs_grad(gw, ref, tol=1e-4):
+    """Per component, relative to the component (or to a floor of 1e-3 of
+    the largest component of its own group for entries near zero)."""
+    groups = [slice(0, 2), slice(2, 4), slice(4, 8), slice(8, None)]
+    for g in groups:
+        r = ref[g]
+        if r.size == 0:
+            continue
+        floor = 1e-3 * np.max(np.abs(r))
+        err = np.abs(gw[g] - r) / np.maximum(np.abs(r), floor)
+        assert err.max() <= tol, (g, err.max(), gw[g], r)
+
+
+@pytest.mark.parametrize("interp", [1, 2])
+def test_gradients_vs_oracle(dfr, orc, interp):
+    c, true_w = grad_case(160)
+    print(f"grad interp={interp} size=160", flush=True)
+    src = torch.from_numpy(c.src).cuda()
+    rng = np.random.default_rng(3)
+    g = rng.normal(0, 1, c.out_shape).astype(np.float32)
+    g *= interior_mask(orc, c, true_w)
+    gs, gw = dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, INTERPS[interp],
+                                    torch.from_numpy(g).cuda())
+    torch.cuda.synchronize()
+    ogs, ogw = orc.grad(c.src, c.src_wcs, c.tgt_wcs, c.out_shape, interp, g.astype(np.float64))
+    gs = gs.cpu().numpy().astype(np.float64)
+    # each source pixel sums <= 16 terms g*w/F; positions differ by < 1e-4 px
+    assert np.abs(gs - ogs).max() <= 1e-4 * np.abs(g).max()
+    _compare_wcs_grad(gw.cpu().numpy(), ogw)
+
+
+def test_adjoint_identity_on_gpu(dfr):
+    c, _ = grad_case(200)
+    src = torch.from_numpy(c.src).cuda()
+    g = torch.randn(c.out_shape, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    out, _ = dfr.reproject(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic")
+    gs, _ = dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic", g,
+                                   want_wcs=False)
+    lhs = torch.sum(out.double() * g.double())
+    rhs = torch.sum(src.double() * gs.double())
+    scale = torch.sum(torch.abs(out.double() * g.double()))
+    assert abs((lhs - rhs).item()) <= 1e-5 * scale.item()
+
+
+def test_nearest_backward(dfr, orc):
+    c, _ = grad_case(96)
+    src = torch.from_numpy(c.src).cuda()
+    g = np.random.default_rng(5).normal(0, 1, c.out_shape).astype(np.float32)
+    gs, gw = dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, "nearest",
+                                    torch.from_numpy(g).cuda())
+    ogs, ogw = orc.grad(c.src, c.src_wcs, c.tgt_wcs, c.out_shape, 0, g.astype(np.float64))
+    assert np.abs(gs.cpu().numpy() - ogs).max() <= 1e-5 * np.abs(g).max()
+    assert np.all(gw.cpu().numpy()[[0, 1, 4, 5, 6, 7]] == 0.0)
+
+
+def test_full_size_alignment_gradient(dfr, orc):
+    """The 2048^2 bicubic alignment case: loss against the reference
+    reprojection under the true WCS, gradient at the perturbed WCS."""
+    c, true_w = grad_case(2048)
+    src = torch.from_numpy(c.src).cuda()
+    mask = torch.from_numpy(interior_mask(orc, c, true_w).astype(np.float32)).cuda()
+    ref, _ = dfr.reproject(src, true_w, c.tgt_wcs, c.out_shape, "bicubic")
+    out, _ = dfr.reproject(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic")
+    loss, g = dfr.sq_residual(out, ref, mask)
+    gs, gw = dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic", g)
+    torch.cuda.synchronize()
+    gn = g.cpu().numpy().astype(np.float64)
+    ogs, ogw = orc.grad(c.src, c.src_wcs, c.tgt_wcs, c.out_shape, 2, gn)
+    print("loss", loss.item(), "grad_wcs", gw.cpu().numpy()[:8], "oracle", ogw[:8], flush=True)
+    _compare_wcs_grad(gw.cpu().numpy(), ogw)
+    assert np.abs(gs.cpu().numpy() - ogs).max() <= 1e-4 * np.abs(gn).max()
+
+
+def test_sq_residual_kernel(dfr):
+    gen = torch.Generator("cuda").manual_seed(2)
+    a = torch.randn(1000, 777, device="cuda", generator=gen)
+    b = torch.randn(1000, 777, device="cuda", generator=gen)
+    m = (torch.rand(1000, 777, device="cuda", generator=gen) > 0.3).float()
+    loss, g = dfr.sq_residual(a, b, m)
+    r = (a - b).double()
+    ref = torch.sum(m.double() * r * r)
+    assert abs(loss.item() - ref.item()) <= 1e-12 * abs(ref.item())
+    assert torch.equal(g, 2.0 * m * (a - b))
+    loss2, _ = dfr.sq_residual(a, b)
+    assert abs(loss2.item() - torch.sum(r * r).item()) <= 1e-12 * torch.sum(r * r).item()
+
+
+def test_autograd_function(dfr):
+    c, true_w = grad_case(128)
+    src = torch.from_numpy(c.src).cuda().requires_grad_(True)
+    theta = torch.tensor(dfr.wcs_params(c.src_wcs), dtype=torch.float64,
+                         requires_grad=True)
+    ref, _ = dfr.reproject(src.detach(), true_w, c.tgt_wcs, c.out_shape, "bicubic")
+    out = dfr.reproject_differentiable(src, theta, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic")
+    loss = torch.sum((out - ref) ** 2)
+    loss.backward()
+    g = 2.0 * (out.detach() - ref)
+    gs, gw = dfr.reproject_backward(src.detach(), c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic", g)
+    assert torch.allclose(src.grad, gs, rtol=0, atol=1e-5 * gs.abs().max().item())
+    assert torch.allclose(theta.grad, gw.cpu(), rtol=1e-6, atol=0)
+
+
+def test_gradient_descent_reduces_misalignment(dfr):
+    """WCS alignment by gradient descent on image residuals (CRPIX only)."""
+    c, true_w = grad_case(256)
+    src = torch.from_numpy(c.src).cuda()
+    ref, _ = dfr.reproject(src, true_w, c.tgt_wcs, c.out_shape, "bicubic")
+    w = c.src_wcs.copy(crpix=(c.src_wcs.crpix[0] + 0.4, c.src_wcs.crpix[1] - 0.3))
+    err0 = np.hypot(w.crpix[0] - true_w.crpix[0], w.crpix[1] - true_w.crpix[1])
+    for _ in range(20):
+        out, _ = dfr.reproject(src, w, c.tgt_wcs, c.out_shape, "bicubic")
+        loss, g = dfr.sq_residual(out, ref)
+        _, gw = dfr.reproject_backward(src, w, c.tgt_wcs, c.out_shape, "bicubic", g,
+                                       want_src=False)
+        gc = gw.cpu().numpy()[2:4]
+        step = 0.2 / (np.abs(gc).max() + 1e-30) * np.minimum(1.0, np.abs(gc).max())
+        w = w.copy(crpix=(w.crpix[0] - 0.05 * np.sign(gc[0]) * min(1, abs(gc[0]) * step),
+                          w.crpix[1] - 0.05 * np.sign(gc[1]) * min(1, abs(gc[1]) * step)))
+    err1 = np.hypot(w.crpix[0] - true_w.crpix[0], w.crpix[1] - true_w.crpix[1])
+    assert err1 < 0.5 * err0
