@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
   for (int s = 0; s < NS; ++s) acc[s] = 0.0f;
 
   TileCtx c;
-  if (tile_anchors<INTERP, NP>(P, G, tile, sh, c)) {
+  if (tile_anchors<INTERP, SORD, NP>(P, G, tile, sh, c)) {
     TilePos<NP> T;
     tile_positions<INTERP, SORD, NP>(P, G, sh, c, T);
     const int bw = T.empty ? 0 : T.bi1 - T.bi0 + 1;

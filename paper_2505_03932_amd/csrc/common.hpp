@@ -11,7 +11,7 @@
 // M = [east | north | centre] the tangent frame of each reference point.
 // H is composed on the host in FP64.
 //
-// Precision split.  Per 16x16 cell of output pixels (a fixed grid, so tile
+// Precision split.  Per 32x32 cell of output pixels (a fixed grid, so tile
 // shape and batching never change results) one lane evaluates the map in
 // FP64 at the cell's anchor pixel and reduces it to small FP32 coefficients:
 // every pixel of the cell then evaluates only offsets from the anchor in
@@ -27,7 +27,8 @@ namespace dfr {
 
 constexpr int kMaxOrder = DFR_MAX_SIP_ORDER;
 constexpr int kMaxCoef = (kMaxOrder + 1) * (kMaxOrder + 2) / 2;  // 55
-constexpr int kCell = 16;       // anchor grid pitch in output pixels (both axes)
+constexpr int kCellLog2 = 5;
+constexpr int kCell = 1 << kCellLog2;  // anchor grid pitch in output pixels (both axes)
 constexpr int kThreads = 256;   // work-group size of every tile kernel
 constexpr int kRun = 4;         // consecutive output pixels per thread and row
 constexpr int kMaxAnchors = 16; // anchors a tile covers at most
@@ -190,6 +191,27 @@ __host__ __device__ __forceinline__ double sip_f64(const double *__restrict__ c,
   return f;
 }
 
+// FP64 Horner with a compile-time order (N < 0: run-time order n).
+template <int N>
+__device__ __forceinline__ double sip_f64_ct(const double *__restrict__ c, int n, double x,
+                                             double y) {
+  if constexpr (N < 0) {
+    return sip_f64(c, n, x, y);
+  } else if constexpr (N == 0) {
+    return 0.0;
+  } else {
+    double f = 0.0;
+#pragma unroll
+    for (int p = N; p >= 0; --p) {
+      double in = c[tri9(p, N - p)];
+#pragma unroll
+      for (int q = N - p - 1; q >= 0; --q) in = fma(in, y, c[tri9(p, q)]);
+      f = (p == N) ? in : fma(f, x, in);
+    }
+    return f;
+  }
+}
+
 // ----------------------------------------------------------- positions --
 
 // Source position of target pixel (x, y) entirely in FP64 (no anchor).
@@ -219,10 +241,37 @@ __host__ __device__ __forceinline__ bool position_f64(const FramePlan &P, double
   return __builtin_isfinite(xs) && __builtin_isfinite(ys);
 }
 
+// position_f64 with the source SIP order known at compile time (when SORD
+// >= 0; the padded coefficients make it equal to the run-time version).
+template <int SORD>
+__device__ __forceinline__ bool position_f64_ct(const FramePlan &P, double x, double y,
+                                                double &xs, double &ys) {
+  double u = x - P.tcr[0], v = y - P.tcr[1];
+  if (P.t_order > 0) {
+    double du = sip_f64(P.tA, P.t_order, u, v);
+    double dv = sip_f64(P.tB, P.t_order, u, v);
+    u += du;
+    v += dv;
+  }
+  double p = fma(P.H[0], u, fma(P.H[1], v, P.H[2]));
+  double q = fma(P.H[3], u, fma(P.H[4], v, P.H[5]));
+  double w = fma(P.H[6], u, fma(P.H[7], v, P.H[8]));
+  if (!(w > 0.0)) return false;
+  double iw = 1.0 / w;
+  double U = p * iw, V = q * iw;
+  double dU = sip_f64_ct<SORD>(P.sA, P.s_order, U, V);
+  double dV = sip_f64_ct<SORD>(P.sB, P.s_order, U, V);
+  xs = U + dU + P.scr[0];
+  ys = V + dV + P.scr[1];
+  return isfinite(xs) && isfinite(ys);
+}
+
 constexpr double kFar = 268435456.0;  // 2^28: anchors beyond this are out of any image
 
 // FP64 evaluation at the anchor pixel (xa, ya) of a cell.  `support` is how
-// far interpolation taps reach beyond the position (0, 1 or 2 px).
+// far interpolation taps reach beyond the position (0, 1 or 2 px).  SORD is
+// the source SIP order when known at compile time (< 0: read at run time).
+template <int SORD>
 __device__ __forceinline__ void compute_anchor(const FramePlan &P, int xa, int ya, int support,
                                                Anchor &A) {
   double u = (double)xa - P.tcr[0], v = (double)ya - P.tcr[1];
@@ -284,8 +333,13 @@ __device__ __forceinline__ void compute_anchor(const FramePlan &P, int xa, int y
   // with slope L, the cell's source image lies within (1 + 2L) times the
   // affine reach of the anchor while the slope stays below 1/2 over it.
   float fa, fau, fav, fb, fbu, fbv;
-  sip_f32_grad_rt(P.fsA, P.s_order, A.u0s, A.v0s, fa, fau, fav);
-  sip_f32_grad_rt(P.fsB, P.s_order, A.u0s, A.v0s, fb, fbu, fbv);
+  if constexpr (SORD >= 0) {
+    sip_f32_grad<SORD>(P.fsA, A.u0s, A.v0s, fa, fau, fav);
+    sip_f32_grad<SORD>(P.fsB, A.u0s, A.v0s, fb, fbu, fbv);
+  } else {
+    sip_f32_grad_rt(P.fsA, P.s_order, A.u0s, A.v0s, fa, fau, fav);
+    sip_f32_grad_rt(P.fsB, P.s_order, A.u0s, A.v0s, fb, fbu, fbv);
+  }
   double L = (fabs((double)fau) + fabs((double)fav) + fabs((double)fbu) + fabs((double)fbv)) *
              P.s_inv_scale;
   double xs = X0 + (double)fa, ys = Y0 + (double)fb;

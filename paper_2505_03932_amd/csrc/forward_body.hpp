@@ -171,7 +171,7 @@ struct TileCtx {
 
 // Phase 1.  Returns false when no pixel of the tile can reach the source
 // (and skipping is allowed): the caller then only writes "uncovered".
-template <int INTERP, int NP>
+template <int INTERP, int SORD, int NP>
 __device__ __forceinline__ bool tile_anchors(const FramePlan &P, const TileGeom &G, int tile,
                                              TileShared &sh, TileCtx &c) {
   const int tid = threadIdx.x;
@@ -193,7 +193,7 @@ __device__ __forceinline__ bool tile_anchors(const FramePlan &P, const TileGeom 
     int t = 0;
     if (tid < nA) {
       int cy = c.cy0 + tid / c.ncx, cx = c.cx0 + tid % c.ncx;
-      compute_anchor(P, cx * kCell, cy * kCell, TapSupport<INTERP>::hi, sh.anchor[tid]);
+      compute_anchor<SORD>(P, cx * kCell, cy * kCell, TapSupport<INTERP>::hi, sh.anchor[tid]);
       t = sh.anchor[tid].touch;
     }
     unsigned long long any = __ballot(t != 0);
@@ -232,7 +232,7 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     const int y = c.y0 + c.ty + k * c.RP;
-    const int a = ((y >> 4) - c.cy0) * c.ncx + ((c.xr >> 4) - c.cx0);
+    const int a = ((y >> kCellLog2) - c.cy0) * c.ncx + ((c.xr >> kCellLog2) - c.cx0);
     const Anchor &A = sh.anchor[a];
     T.aidx[k] = a;
     T.abx[k] = A.bx;
@@ -487,7 +487,7 @@ __device__ __forceinline__ void tap_origin(float r, int base, int &i0, float &t)
 // Wave 1 of phase 1: FP64 positions at 9 points of the tile's rectangle
 // (clipped to the output), their bounding box grown by the tap support and
 // 2 px, and whether all 9 are valid.
-template <int INTERP>
+template <int INTERP, int SORD>
 __device__ __forceinline__ void tile_box_samples(const FramePlan &P, const TileGeom &G, int x0,
                                                  int y0, int TW, int TH, TileShared &sh) {
   const int lane = threadIdx.x & 63;
@@ -499,7 +499,7 @@ __device__ __forceinline__ void tile_box_samples(const FramePlan &P, const TileG
     const double px = ix == 0 ? x0 : (ix == 1 ? 0.5 * (x0 + xe) : (double)xe);
     const double py = iy == 0 ? y0 : (iy == 1 ? 0.5 * (y0 + ye) : (double)ye);
     double xs, ys;
-    ok = position_f64(P, px, py, xs, ys) && fabs(xs) < 1.0e9 && fabs(ys) < 1.0e9;
+    ok = position_f64_ct<SORD>(P, px, py, xs, ys) && fabs(xs) < 1.0e9 && fabs(ys) < 1.0e9;
     if (ok) {
       imn = (int)floor(xs);
       imx = imn;
@@ -527,10 +527,12 @@ __device__ __forceinline__ void tile_box_samples(const FramePlan &P, const TileG
 // instruction, lanes past the row end masked off.
 __device__ __forceinline__ void dma_box(const FramePlan &P, int bi0, int bj0, int bw, int bh,
                                         float *__restrict__ lds) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const float *__restrict__ s0 = P.src + (int64_t)bj0 * P.pitch + bi0;
+#pragma unroll 1
   for (int r = wave; r < bh; r += kThreads / 64) {
     const float *sr = s0 + (int64_t)r * P.pitch;
+#pragma unroll 1
     for (int c0 = 0; c0 < bw; c0 += 64) {
       if (c0 + lane < bw)
         __builtin_amdgcn_global_load_lds(sr + c0 + lane, lds + r * bw + c0, 4, 0, 0);
@@ -556,7 +558,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
     int t = 0, okc = 1;
     if (tid < nA) {
       int cy = cy0 + tid / ncx, cx = cx0 + tid % ncx;
-      compute_anchor(P, cx * kCell, cy * kCell, TapSupport<INTERP>::hi, sh.anchor[tid]);
+      compute_anchor<SORD>(P, cx * kCell, cy * kCell, TapSupport<INTERP>::hi, sh.anchor[tid]);
       t = sh.anchor[tid].touch;
       okc = sh.anchor[tid].ok;
     }
@@ -566,7 +568,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
       sh.cells_ok = bad == 0ull;
     }
   } else if (wave == 1) {
-    tile_box_samples<INTERP>(P, G, x0, y0, TW, TH, sh);
+    tile_box_samples<INTERP, SORD>(P, G, x0, y0, TW, TH, sh);
   }
   __syncthreads();
 
@@ -605,55 +607,72 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   float rx[NP][kRun], ry[NP][kRun];
   int abx[NP], aby[NP];
   unsigned valid = 0u;
+  if (interior && !G.debug && INTERP != DFR_NEAREST) {
+    // every cell is valid throughout and the tile lies inside the output
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    const int y = y0 + ty + k * RP;
-    const Anchor &A = sh.anchor[((y >> 4) - cy0) * ncx + ((xr >> 4) - cx0)];
-    abx[k] = A.bx;
-    aby[k] = A.by;
-    const float dy = (float)(y & (kCell - 1));
+    for (int k = 0; k < NP; ++k) {
+      const int y = y0 + ty + k * RP;
+      const Anchor &A = sh.anchor[((y >> kCellLog2) - cy0) * ncx + ((xr >> kCellLog2) - cx0)];
+      abx[k] = A.bx - bi0;
+      aby[k] = A.by - bj0;
+      const float dy = (float)(y & (kCell - 1));
 #pragma unroll
-    for (int e = 0; e < kRun; ++e) {
-      const int x = xr + e;
-      float px, py;
-      bool ok = pixel_position<SORD>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy, px,
-                                     py);
-      ok = ok && (y < G.out_h) && (x < G.out_w);
-      double dbx = 0.0, dby = 0.0;
-      bool exact = false;
-      if constexpr (INTERP == DFR_NEAREST) {
-        // a rounding decision within reach of the FP32 error: decide in FP64
-        float tx_ = px - floorf(px), ty_ = py - floorf(py);
-        if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
-          double xs, ys;
-          ok = position_f64(P, (double)x, (double)y, xs, ys) && fabs(xs - A.bx) < 1.0e7 &&
-               fabs(ys - A.by) < 1.0e7;
-          if (ok) {
-            px = (float)(rint(xs) - (double)A.bx);
-            py = (float)(rint(ys) - (double)A.by);
-            exact = true;
-            dbx = xs;
-            dby = ys;
+      for (int e = 0; e < kRun; ++e)
+        pixel_position<SORD>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy, rx[k][e],
+                             ry[k][e]);
+    }
+    valid = ~0u;
+  } else {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int y = y0 + ty + k * RP;
+      const Anchor &A = sh.anchor[((y >> kCellLog2) - cy0) * ncx + ((xr >> kCellLog2) - cx0)];
+      abx[k] = A.bx - bi0;
+      aby[k] = A.by - bj0;
+      const float dy = (float)(y & (kCell - 1));
+#pragma unroll
+      for (int e = 0; e < kRun; ++e) {
+        const int x = xr + e;
+        float px, py;
+        bool ok = pixel_position<SORD>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy,
+                                       px, py);
+        ok = ok && (y < G.out_h) && (x < G.out_w);
+        double dbx = 0.0, dby = 0.0;
+        bool exact = false;
+        if constexpr (INTERP == DFR_NEAREST) {
+          // a rounding decision within reach of the FP32 error: decide in FP64
+          float tx_ = px - floorf(px), ty_ = py - floorf(py);
+          if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
+            double xs, ys;
+            ok = position_f64(P, (double)x, (double)y, xs, ys) && fabs(xs - A.bx) < 1.0e7 &&
+                 fabs(ys - A.by) < 1.0e7;
+            if (ok) {
+              px = (float)(rint(xs) - (double)A.bx);
+              py = (float)(rint(ys) - (double)A.by);
+              exact = true;
+              dbx = xs;
+              dby = ys;
+            }
           }
         }
-      }
-      rx[k][e] = px;
-      ry[k][e] = py;
-      if (G.debug && y < G.out_h && x < G.out_w) {
-        double2 d;
-        if (!ok) {
-          d.x = __builtin_nan("");
-          d.y = d.x;
-        } else if (exact) {
-          d.x = dbx;
-          d.y = dby;
-        } else {
-          d.x = (double)A.bx + (double)px;
-          d.y = (double)A.by + (double)py;
+        rx[k][e] = px;
+        ry[k][e] = py;
+        if (G.debug && y < G.out_h && x < G.out_w) {
+          double2 d;
+          if (!ok) {
+            d.x = __builtin_nan("");
+            d.y = d.x;
+          } else if (exact) {
+            d.x = dbx;
+            d.y = dby;
+          } else {
+            d.x = (double)A.bx + (double)px;
+            d.y = (double)A.by + (double)py;
+          }
+          reinterpret_cast<double2 *>(G.debug)[(int64_t)y * G.out_w + x] = d;
         }
-        reinterpret_cast<double2 *>(G.debug)[(int64_t)y * G.out_w + x] = d;
+        if (ok) valid |= 1u << (k * kRun + e);
       }
-      if (ok) valid |= 1u << (k * kRun + e);
     }
   }
 
@@ -661,21 +680,24 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   constexpr int SPAN = TapSupport<INTERP>::lo + TapSupport<INTERP>::hi;
-  // every tap of every pixel inside the staged box?
-  bool fast = interior;
+  // Fast path: every tap of every pixel inside the staged box.  With
+  // b = box-relative anchor base, floor(r) + b - lo must lie in
+  // [0, extent - 1 - SPAN]: r in [lo - b, extent - SPAN + lo - b) (rint:
+  // shifted by one half).
+  bool fast = interior && valid == ~0u;
   if (fast) {
+    constexpr float half = INTERP == DFR_NEAREST ? 0.5f : 0.0f;
     bool inside = true;
 #pragma unroll
-    for (int k = 0; k < NP; ++k)
+    for (int k = 0; k < NP; ++k) {
+      const float lx = (float)(TapSupport<INTERP>::lo - abx[k]) - half;
+      const float hx = (float)(bw - SPAN + TapSupport<INTERP>::lo - abx[k]) - half;
+      const float ly = (float)(TapSupport<INTERP>::lo - aby[k]) - half;
+      const float hy = (float)(bh - SPAN + TapSupport<INTERP>::lo - aby[k]) - half;
 #pragma unroll
-      for (int e = 0; e < kRun; ++e) {
-        int i0, j0;
-        float t_, s_;
-        tap_origin<INTERP>(rx[k][e], abx[k] - bi0, i0, t_);
-        tap_origin<INTERP>(ry[k][e], aby[k] - bj0, j0, s_);
-        inside = inside && ((unsigned)i0 <= (unsigned)(bw - 1 - SPAN)) &&
-                 ((unsigned)j0 <= (unsigned)(bh - 1 - SPAN));
-      }
+      for (int e = 0; e < kRun; ++e)
+        inside = inside && rx[k][e] >= lx && rx[k][e] < hx && ry[k][e] >= ly && ry[k][e] < hy;
+    }
     fast = __ballot(!inside) == 0ull;
   }
   const float a = G.cubic_a;
@@ -690,8 +712,8 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
       for (int e = 0; e < kRun; ++e) {
         int i0, j0;
         float t_, s_;
-        tap_origin<INTERP>(rx[k][e], abx[k] - bi0, i0, t_);
-        tap_origin<INTERP>(ry[k][e], aby[k] - bj0, j0, s_);
+        tap_origin<INTERP>(rx[k][e], abx[k], i0, t_);
+        tap_origin<INTERP>(ry[k][e], aby[k], j0, s_);
         if constexpr (INTERP == DFR_NEAREST) {
           o[e] = fl(i0, j0);
         } else if constexpr (INTERP == DFR_BILINEAR) {
@@ -711,7 +733,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
     return;
   }
   // general path: source coordinates, zero padding, footprint normalisation;
-  // taps come from LDS when the pixel's taps are inside the staged box
+  // taps come from LDS when the pixel's in-image taps are inside the box
   auto fl = [&](int i, int j) -> float { return lds[__umul24(j - bj0, bw) + (i - bi0)]; };
   auto fg = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
 #pragma unroll
@@ -726,9 +748,8 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
       if (valid & (1u << (k * kRun + e))) {
         int i0, j0;
         float t_, s_;
-        tap_origin<INTERP>(rx[k][e], abx[k], i0, t_);
-        tap_origin<INTERP>(ry[k][e], aby[k], j0, s_);
-        // the in-image part of the tap box must lie in the staged box
+        tap_origin<INTERP>(rx[k][e], abx[k] + bi0, i0, t_);
+        tap_origin<INTERP>(ry[k][e], aby[k] + bj0, j0, s_);
         const bool in_lds = use_lds && max(i0, 0) >= bi0 && min(i0 + SPAN, W - 1) <= bi1 &&
                             max(j0, 0) >= bj0 && min(j0 + SPAN, Hs - 1) <= bj1;
         float ov, fv;
