@@ -35,35 +35,58 @@ def lib():
         if not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        L = C.CDLL(LIB_PATH)
-        dp = C.POINTER(C.c_double)
-        L.orc_pix2world.argtypes = [C.POINTER(OrcWcs), C.c_double, C.c_double, dp, dp]
-        L.orc_world2pix.argtypes = [C.POINTER(OrcWcs), C.c_double, C.c_double, dp, dp]
-        L.orc_world2pix.restype = C.c_int
-        L.orc_world2pix_exact.argtypes = [C.POINTER(OrcWcs), C.c_double, C.c_double, dp, dp]
-        L.orc_world2pix_exact.restype = C.c_int
-        L.orc_pix2world_n.argtypes = [C.POINTER(OrcWcs), C.c_void_p, C.c_int64, C.c_void_p]
-        L.orc_world2pix_n.argtypes = [C.POINTER(OrcWcs), C.c_void_p, C.c_int64, C.c_void_p,
-                                      C.c_void_p, C.c_int]
-        L.orc_reproject_rows.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
-                                         C.POINTER(OrcWcs), C.POINTER(OrcWcs), C.c_int64,
-                                         C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_int,
-                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
-        L.orc_interp_at.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
-                                    C.c_int64, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
-                                    C.c_void_p]
-        L.orc_interp.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_double,
-                                 C.c_double, C.c_int, C.c_double, dp, dp, dp]
-        L.orc_n_params.argtypes = [C.POINTER(OrcWcs)]
-        L.orc_n_params.restype = C.c_int64
-        L.orc_grad.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.POINTER(OrcWcs),
-                               C.POINTER(OrcWcs), C.c_int64, C.c_int64, C.c_int, C.c_double,
-                               C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_sip_eval.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
-        L.orc_sip_eval.restype = C.c_double
-        L.orc_online_cores.restype = C.c_int
-        _lib = L
+        _lib = _configure(C.CDLL(LIB_PATH))
     return _lib
+
+
+class use_library:
+    """Context manager: route this module's calls to another build of
+    oracle.c (the mutation tests plant mistakes in a copy of the source)."""
+
+    def __init__(self, path):
+        self.L = _configure(C.CDLL(path))
+
+    def __enter__(self):
+        global _lib
+        lib()
+        self.saved = _lib
+        _lib = self.L
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
+
+
+def _configure(L):
+    dp = C.POINTER(C.c_double)
+    L.orc_pix2world.argtypes = [C.POINTER(OrcWcs), C.c_double, C.c_double, dp, dp]
+    L.orc_world2pix.argtypes = [C.POINTER(OrcWcs), C.c_double, C.c_double, dp, dp]
+    L.orc_world2pix.restype = C.c_int
+    L.orc_world2pix_exact.argtypes = [C.POINTER(OrcWcs), C.c_double, C.c_double, dp, dp]
+    L.orc_world2pix_exact.restype = C.c_int
+    L.orc_pix2world_n.argtypes = [C.POINTER(OrcWcs), C.c_void_p, C.c_int64, C.c_void_p]
+    L.orc_world2pix_n.argtypes = [C.POINTER(OrcWcs), C.c_void_p, C.c_int64, C.c_void_p,
+                                  C.c_void_p, C.c_int]
+    L.orc_reproject_rows.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
+                                     C.POINTER(OrcWcs), C.POINTER(OrcWcs), C.c_int64,
+                                     C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_int,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+    L.orc_interp_at.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
+                                C.c_int64, C.c_int, C.c_double, C.c_void_p, C.c_void_p,
+                                C.c_void_p]
+    L.orc_interp.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_double,
+                             C.c_double, C.c_int, C.c_double, dp, dp, dp]
+    L.orc_n_params.argtypes = [C.POINTER(OrcWcs)]
+    L.orc_n_params.restype = C.c_int64
+    L.orc_grad.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.POINTER(OrcWcs),
+                           C.POINTER(OrcWcs), C.c_int64, C.c_int64, C.c_int, C.c_double,
+                           C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_sip_eval.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
+    L.orc_sip_eval.restype = C.c_double
+    L.orc_online_cores.restype = C.c_int
+    return L
 
 
 class _W:
