@@ -5,18 +5,14 @@
 // pixels.  Thread (tx, ty) owns NP runs of kRun consecutive pixels in rows
 // ty, ty + RP, ..., so every wave store covers contiguous row segments.
 //
-// Phases (shared by the forward and backward kernels)
-//   1. anchors: lanes 0..nA-1 of wave 0 evaluate the map in FP64 at the
-//      16x16-cell anchors the tile covers (<= 16) -> LDS;
-//   2. positions: every pixel's source position from FP32 offsets to its
-//      cell's anchor (Horner SIP in registers); nearest lanes within 1e-4 px
-//      of a rounding tie are recomputed entirely in FP64;
-//   3. exact bounding box of every in-image tap (wave min/max reductions,
-//      then LDS atomics across the 4 waves): the halo is exactly what the
-//      local Jacobian of the map needs;
-//   4. the box is staged in LDS with coalesced row loads (global gathers if
-//      it exceeds the LDS budget);
-//   5. forward: gather, footprint, normalisation and row stores.
+// Two schedules share the per-pixel position code:
+//   * tile_anchors / tile_positions / stage_box (used by the backward
+//     kernel): anchors, then positions with the exact bounding box of all
+//     in-image taps (wave min/max reductions + LDS atomics), then a
+//     synchronous copy of that box into LDS;
+//   * forward_tile: anchors and a sampled source box in parallel, the box
+//     staged by asynchronous DMA while the positions are computed (see the
+//     comment above forward_tile).
 #pragma once
 
 #include "common.hpp"
@@ -75,72 +71,6 @@ __device__ __forceinline__ bool pixel_position(const FramePlan &P, const Anchor 
     geom->vs = vs;
   }
   return (A.sgn * den > 0.0f) && (fabsf(rx) < 1.0e7f) && (fabsf(ry) < 1.0e7f);
-}
-
-// Interpolation of one pixel.  `fetch(i, j)` reads source pixel (i, j) for
-// in-image taps.
-template <int INTERP, typename Fetch>
-__device__ __forceinline__ void interpolate(int bx, int by, float rx, float ry, int W, int H,
-                                            float cubic_a, const Fetch &fetch, float &out,
-                                            float &fp) {
-  if constexpr (INTERP == DFR_NEAREST) {
-    int i = bx + (int)rintf(rx);
-    int j = by + (int)rintf(ry);
-    bool in = ((unsigned)i < (unsigned)W) && ((unsigned)j < (unsigned)H);
-    out = in ? fetch(i, j) : 0.0f;
-    fp = in ? 1.0f : 0.0f;
-  } else if constexpr (INTERP == DFR_BILINEAR) {
-    float fx = floorf(rx), fy = floorf(ry);
-    float t = rx - fx, s = ry - fy;
-    int i0 = bx + (int)fx, j0 = by + (int)fy;
-    bool ix0 = (unsigned)i0 < (unsigned)W, ix1 = (unsigned)(i0 + 1) < (unsigned)W;
-    bool iy0 = (unsigned)j0 < (unsigned)H, iy1 = (unsigned)(j0 + 1) < (unsigned)H;
-    float wx0 = ix0 ? 1.0f - t : 0.0f, wx1 = ix1 ? t : 0.0f;
-    float wy0 = iy0 ? 1.0f - s : 0.0f, wy1 = iy1 ? s : 0.0f;
-    float v00 = (ix0 && iy0) ? fetch(i0, j0) : 0.0f;
-    float v01 = (ix1 && iy0) ? fetch(i0 + 1, j0) : 0.0f;
-    float v10 = (ix0 && iy1) ? fetch(i0, j0 + 1) : 0.0f;
-    float v11 = (ix1 && iy1) ? fetch(i0 + 1, j0 + 1) : 0.0f;
-    float S = fmaf(wy0, fmaf(wx0, v00, wx1 * v01), wy1 * fmaf(wx0, v10, wx1 * v11));
-    bool all_in = ix0 && ix1 && iy0 && iy1;
-    float F = all_in ? 1.0f : (wx0 + wx1) * (wy0 + wy1);
-    out = all_in ? S : (F > 0.0f ? S * __builtin_amdgcn_rcpf(F) : 0.0f);
-    fp = F > 0.0f ? F : 0.0f;
-  } else {
-    float fx = floorf(rx), fy = floorf(ry);
-    float t = rx - fx, s = ry - fy;
-    int i0 = bx + (int)fx - 1, j0 = by + (int)fy - 1;
-    float wx[4], wy[4];
-    keys_weights(t, cubic_a, wx);
-    keys_weights(s, cubic_a, wy);
-    bool inx[4], iny[4];
-    bool all_in = true;
-    float Fx = 0.0f, Fy = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      inx[k] = (unsigned)(i0 + k) < (unsigned)W;
-      iny[k] = (unsigned)(j0 + k) < (unsigned)H;
-      all_in = all_in && inx[k] && iny[k];
-      wx[k] = inx[k] ? wx[k] : 0.0f;
-      wy[k] = iny[k] ? wy[k] : 0.0f;
-      Fx += wx[k];
-      Fy += wy[k];
-    }
-    float S = 0.0f;
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      float row = 0.0f;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        float v = (inx[k] && iny[l]) ? fetch(i0 + k, j0 + l) : 0.0f;
-        row = fmaf(wx[k], v, row);
-      }
-      S = fmaf(wy[l], row, S);
-    }
-    float F = all_in ? 1.0f : Fx * Fy;
-    out = all_in ? S : (F > 0.0f ? S * __builtin_amdgcn_rcpf(F) : 0.0f);
-    fp = F > 0.0f ? F : 0.0f;
-  }
 }
 
 // LDS scratch of a tile kernel besides the dynamic source tile.
