@@ -92,6 +92,8 @@ struct alignas(16) Anchor {
   int32_t bx, by;                // integer parts of the anchor source position
   int32_t touch;                 // 0 when no pixel of the cell can reach the source
   int32_t ok;                    // every pixel of the cell has a valid, finite position
+  float jx[2], jy[2];            // d(source position)/d(target pixel) at the anchor
+  float sx0, sy0;                // source position at the anchor minus (bx, by)
 };
 
 // ------------------------------------------------------ SIP polynomials --
@@ -114,14 +116,23 @@ __device__ __forceinline__ float sip_f32(const float *__restrict__ c, float x, f
   }
 }
 
-// Same with a run-time order (target side and high orders).
+// Same with a run-time order n <= kMaxOrder.  Fully unrolled over the
+// maximum order with uniform guards, so the coefficient array is never
+// indexed dynamically (a dynamically indexed kernel-argument array can make
+// the compiler copy the whole plan to private memory).  The coefficients
+// past order n are zero, so fma(0, y, c) = c keeps this bit-identical to a
+// loop over the first n orders.
 __device__ __forceinline__ float sip_f32_rt(const float *__restrict__ c, int n, float x, float y) {
   if (n <= 0) return 0.0f;
   float f = 0.0f;
-  for (int p = n; p >= 0; --p) {
-    float in = c[tri9(p, n - p)];
-    for (int q = n - p - 1; q >= 0; --q) in = fmaf(in, y, c[tri9(p, q)]);
-    f = (p == n) ? in : fmaf(f, x, in);
+#pragma unroll
+  for (int p = kMaxOrder; p >= 0; --p) {
+    if (p > n) continue;
+    float in = 0.0f;
+#pragma unroll
+    for (int q = kMaxOrder - p; q >= 0; --q)
+      if (p + q <= n) in = fmaf(in, y, c[tri9(p, q)]);
+    f = fmaf(f, x, in);
   }
   return f;
 }
@@ -155,31 +166,47 @@ __device__ __forceinline__ void sip_f32_grad(const float *__restrict__ c, float 
   }
 }
 
-// Value and partial derivatives with a run-time order.
+// Value and partial derivatives with a run-time order (unrolled as above).
 __device__ __forceinline__ void sip_f32_grad_rt(const float *__restrict__ c, int n, float x,
                                                 float y, float &f, float &fx, float &fy) {
   f = 0.0f;
   fx = 0.0f;
   fy = 0.0f;
   if (n <= 0) return;
-  for (int p = n; p >= 0; --p) {
-    float in = c[tri9(p, n - p)];
-    float din = 0.0f;
-    for (int q = n - p - 1; q >= 0; --q) {
+#pragma unroll
+  for (int p = kMaxOrder; p >= 0; --p) {
+    if (p > n) continue;
+    float in = 0.0f, din = 0.0f;
+#pragma unroll
+    for (int q = kMaxOrder - p; q >= 0; --q) {
+      if (p + q > n) continue;
       din = fmaf(din, y, in);
       in = fmaf(in, y, c[tri9(p, q)]);
     }
-    if (p == n) {
-      f = in;
-      fy = din;
-    } else {
-      fx = fmaf(fx, x, f);
-      f = fmaf(f, x, in);
-      fy = fmaf(fy, x, din);
-    }
+    fx = fmaf(fx, x, f);
+    f = fmaf(f, x, in);
+    fy = fmaf(fy, x, din);
   }
 }
 
+// FP64, run-time order, unrolled (device).
+__device__ __forceinline__ double sip_f64_dev(const double *__restrict__ c, int n, double x,
+                                              double y) {
+  if (n <= 0) return 0.0;
+  double f = 0.0;
+#pragma unroll
+  for (int p = kMaxOrder; p >= 0; --p) {
+    if (p > n) continue;
+    double in = 0.0;
+#pragma unroll
+    for (int q = kMaxOrder - p; q >= 0; --q)
+      if (p + q <= n) in = fma(in, y, c[tri9(p, q)]);
+    f = fma(f, x, in);
+  }
+  return f;
+}
+
+// Host: loops (used by the FP64 set-up on the host).
 __host__ __device__ __forceinline__ double sip_f64(const double *__restrict__ c, int n, double x, double y) {
   if (n <= 0) return 0.0;
   double f = 0.0;
@@ -196,7 +223,7 @@ template <int N>
 __device__ __forceinline__ double sip_f64_ct(const double *__restrict__ c, int n, double x,
                                              double y) {
   if constexpr (N < 0) {
-    return sip_f64(c, n, x, y);
+    return sip_f64_dev(c, n, x, y);
   } else if constexpr (N == 0) {
     return 0.0;
   } else {
@@ -248,8 +275,8 @@ __device__ __forceinline__ bool position_f64_ct(const FramePlan &P, double x, do
                                                 double &xs, double &ys) {
   double u = x - P.tcr[0], v = y - P.tcr[1];
   if (P.t_order > 0) {
-    double du = sip_f64(P.tA, P.t_order, u, v);
-    double dv = sip_f64(P.tB, P.t_order, u, v);
+    double du = sip_f64_dev(P.tA, P.t_order, u, v);
+    double dv = sip_f64_dev(P.tB, P.t_order, u, v);
     u += du;
     v += dv;
   }
@@ -284,8 +311,8 @@ __device__ __forceinline__ void compute_anchor(const FramePlan &P, int xa, int y
     A.tvs = (float)(v * P.t_inv_scale);
     A.ta0 = sip_f32_rt(P.ftA, P.t_order, A.tus, A.tvs);
     A.tb0 = sip_f32_rt(P.ftB, P.t_order, A.tus, A.tvs);
-    double du = sip_f64(P.tA, P.t_order, u, v);
-    double dv = sip_f64(P.tB, P.t_order, u, v);
+    double du = sip_f64_dev(P.tA, P.t_order, u, v);
+    double dv = sip_f64_dev(P.tB, P.t_order, u, v);
     u += du;
     v += dv;
   }
@@ -343,6 +370,17 @@ __device__ __forceinline__ void compute_anchor(const FramePlan &P, int xa, int y
   double L = (fabs((double)fau) + fabs((double)fav) + fabs((double)fbu) + fabs((double)fbv)) *
              P.s_inv_scale;
   double xs = X0 + (double)fa, ys = Y0 + (double)fb;
+  // linear model of the cell's source positions (used to size the LDS box)
+  {
+    const float s_ = (float)P.s_inv_scale;
+    const float apu = fau * s_, apv = fav * s_, bpu = fbu * s_, bpv = fbv * s_;
+    A.jx[0] = (1.0f + apu) * A.g1 + apv * A.f1;
+    A.jx[1] = (1.0f + apu) * A.g2 + apv * A.f2;
+    A.jy[0] = bpu * A.g1 + (1.0f + bpv) * A.f1;
+    A.jy[1] = bpu * A.g2 + (1.0f + bpv) * A.f2;
+    A.sx0 = A.c0x + fa;
+    A.sy0 = A.c0y + fb;
+  }
   double kk = (fabs(H[6]) + fabs(H[7])) * fabs(iw) * 2.0 * kCell;
   // w > 0 at the anchor and |k . d| < 1/4 over the cell: w > 0 at every pixel
   A.ok = (w > 0.0 && kk < 0.5) ? 1 : 0;

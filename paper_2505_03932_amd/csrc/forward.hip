@@ -8,7 +8,9 @@
 namespace dfr {
 
 template <int INTERP, int SORD, int NP>
-__global__ __launch_bounds__(kThreads) void reproject_tiles(FramePlan P, TileGeom G) {
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(NP >= 4 ? 4 : (INTERP == DFR_BILINEAR ? 8 : 6))))
+void reproject_tiles(FramePlan P, TileGeom G) {
   extern __shared__ float lds[];
   __shared__ TileShared sh;
   forward_tile<INTERP, SORD, NP>(P, G, xcd_tile(blockIdx.x, G.n_tiles), lds, sh);
@@ -120,8 +122,8 @@ __device__ __forceinline__ bool position_trig(const FramePlan &P, const TrigPlan
   const double R0 = 57.295779513082320876798;  // 180 / pi
   double u = x - P.tcr[0], v = y - P.tcr[1];
   if (P.t_order > 0) {
-    double du = sip_f64(P.tA, P.t_order, u, v);
-    double dv = sip_f64(P.tB, P.t_order, u, v);
+    double du = sip_f64_dev(P.tA, P.t_order, u, v);
+    double dv = sip_f64_dev(P.tB, P.t_order, u, v);
     u += du;
     v += dv;
   }
@@ -158,8 +160,8 @@ __device__ __forceinline__ bool position_trig(const FramePlan &P, const TrigPlan
   double U = T.scdi[0] * xp + T.scdi[1] * yp;
   double V = T.scdi[2] * xp + T.scdi[3] * yp;
   if (P.s_order > 0) {
-    double dU = sip_f64(P.sA, P.s_order, U, V);
-    double dV = sip_f64(P.sB, P.s_order, U, V);
+    double dU = sip_f64_dev(P.sA, P.s_order, U, V);
+    double dV = sip_f64_dev(P.sB, P.s_order, U, V);
     U += dU;
     V += dV;
   }
@@ -176,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void reproject_f64(FramePlan P, TrigPlan 
        idx += (int64_t)gridDim.x * kThreads) {
     const int y = (int)(idx / G.out_w), x = (int)(idx - (int64_t)y * G.out_w);
     double xs = 0.0, ys = 0.0;
-    bool ok = TRIG ? position_trig(P, T, x, y, xs, ys) : position_f64(P, x, y, xs, ys);
+    bool ok = TRIG ? position_trig(P, T, x, y, xs, ys) : position_f64_ct<kRtOrder>(P, x, y, xs, ys);
     ok = ok && fabs(xs) < 4.0e15 && fabs(ys) < 4.0e15;
     double o = 0.0, f = 0.0;
     if (ok && P.src_h > 0 && P.src_w > 0) interp_f64<INTERP>(P, xs, ys, (double)G.cubic_a, o, f);

@@ -182,7 +182,7 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
         float tx_ = px - floorf(px), ty_ = py - floorf(py);
         if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
           double xs, ys;
-          ok = position_f64(P, (double)x, (double)y, xs, ys) && fabs(xs - A.bx) < 1.0e7 &&
+          ok = position_f64_ct<SORD>(P, (double)x, (double)y, xs, ys) && fabs(xs - A.bx) < 1.0e7 &&
                fabs(ys - A.by) < 1.0e7;
           if (ok) {
             px = (float)(rint(xs) - (double)A.bx);
@@ -276,6 +276,21 @@ __device__ __forceinline__ void store_run(float *__restrict__ base, int64_t off,
 __device__ __forceinline__ bool vector_stores_ok(const FramePlan &P, const TileGeom &G) {
   return ((G.out_w & (kRun - 1)) == 0) && ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0) &&
          (P.fp == nullptr || (reinterpret_cast<uintptr_t>(P.fp) & 15) == 0);
+}
+
+// Nearest: the FP64 rounding decision for a pixel whose FP32 position lies
+// within 1e-4 px of a tie (rare).  Writes the rounded position relative to
+// (bx, by); returns false if the pixel has no source position.
+__device__ __forceinline__ bool nearest_exact(const FramePlan &P, int x, int y, int bx,
+                                                       int by, float &px, float &py,
+                                                       double &xs, double &ys) {
+  bool ok = position_f64_ct<kRtOrder>(P, (double)x, (double)y, xs, ys) && fabs(xs - bx) < 1.0e7 &&
+            fabs(ys - by) < 1.0e7;
+  if (ok) {
+    px = (float)(rint(xs) - (double)bx);
+    py = (float)(rint(ys) - (double)by);
+  }
+  return ok;
 }
 
 // -------------------------------------------------------------- forward --
@@ -483,22 +498,59 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   const int ty = tid >> lg, xr = x0 + (tid & ((1 << lg) - 1)) * kRun;
   const int W = P.src_w, Hs = P.src_h;
 
-  // ---- 1. anchors (wave 0) and the source box (wave 1), FP64
+  // ---- 1. anchors (FP64) and, from their linear models, the source box
   if (wave == 0) {
+    constexpr int lo = TapSupport<INTERP>::lo + 2, hi = TapSupport<INTERP>::hi + 2;
     int t = 0, okc = 1;
+    int imn = 0x3fffffff, imx = -0x3fffffff, jmn = 0x3fffffff, jmx = -0x3fffffff;
     if (tid < nA) {
-      int cy = cy0 + tid / ncx, cx = cx0 + tid % ncx;
-      compute_anchor<SORD>(P, cx * kCell, cy * kCell, TapSupport<INTERP>::hi, sh.anchor[tid]);
-      t = sh.anchor[tid].touch;
-      okc = sh.anchor[tid].ok;
+      const int cy = cy0 + tid / ncx, cx = cx0 + tid % ncx;
+      const int xa = cx * kCell, ya = cy * kCell;
+      Anchor &A = sh.anchor[tid];
+      compute_anchor<SORD>(P, xa, ya, TapSupport<INTERP>::hi, A);
+      t = A.touch;
+      okc = A.ok;
+      // the part of the cell inside the tile and the output, as offsets
+      const float ux = (float)(min(xa + kCell, min(x0 + TW, G.out_w)) - 1 - xa);
+      const float vy0 = (float)(max(ya, y0) - ya);
+      const float vy1 = (float)(min(ya + kCell, min(y0 + TH, G.out_h)) - 1 - ya);
+      // extremes of the linear model over that rectangle (+ curvature slack
+      // from the projective denominator), relative to (bx, by)
+      const float curv = (fabsf(A.k1) + fabsf(A.k2)) * (float)kCell;
+      const float ex = fabsf(A.jx[0]) * ux + fabsf(A.jx[1]) * fmaxf(vy1, 0.0f);
+      const float ey = fabsf(A.jy[0]) * ux + fabsf(A.jy[1]) * fmaxf(vy1, 0.0f);
+      const float mx = ex * curv, my = ey * curv;
+      const float x_a = A.sx0 + fminf(0.0f, A.jx[0] * ux) + fminf(A.jx[1] * vy0, A.jx[1] * vy1) - mx;
+      const float x_b = A.sx0 + fmaxf(0.0f, A.jx[0] * ux) + fmaxf(A.jx[1] * vy0, A.jx[1] * vy1) + mx;
+      const float y_a = A.sy0 + fminf(0.0f, A.jy[0] * ux) + fminf(A.jy[1] * vy0, A.jy[1] * vy1) - my;
+      const float y_b = A.sy0 + fmaxf(0.0f, A.jy[0] * ux) + fmaxf(A.jy[1] * vy0, A.jy[1] * vy1) + my;
+      if (okc && fabsf(x_a) < 1.0e7f && fabsf(x_b) < 1.0e7f && fabsf(y_a) < 1.0e7f &&
+          fabsf(y_b) < 1.0e7f) {
+        imn = A.bx + (int)floorf(x_a) - lo;
+        imx = A.bx + (int)floorf(x_b) + hi;
+        jmn = A.by + (int)floorf(y_a) - lo;
+        jmx = A.by + (int)floorf(y_b) + hi;
+      } else {
+        okc = 0;
+      }
+    }
+#pragma unroll
+    for (int m = kMaxAnchors / 2; m >= 1; m >>= 1) {
+      imn = min(imn, __shfl_xor(imn, m, 64));
+      imx = max(imx, __shfl_xor(imx, m, 64));
+      jmn = min(jmn, __shfl_xor(jmn, m, 64));
+      jmx = max(jmx, __shfl_xor(jmx, m, 64));
     }
     const unsigned long long any = __ballot(t != 0), bad = __ballot(okc == 0);
     if (tid == 0) {
       sh.touch = any != 0ull;
       sh.cells_ok = bad == 0ull;
+      sh.box_ok = bad == 0ull;
+      sh.box[0] = imn;
+      sh.box[1] = imx;
+      sh.box[2] = jmn;
+      sh.box[3] = jmx;
     }
-  } else if (wave == 1) {
-    tile_box_samples<INTERP, SORD>(P, G, x0, y0, TW, TH, sh);
   }
   __syncthreads();
 
@@ -537,7 +589,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   float rx[NP][kRun], ry[NP][kRun];
   int abx[NP], aby[NP];
   unsigned valid = 0u;
-  if (interior && !G.debug && INTERP != DFR_NEAREST) {
+  if (interior && !G.debug) {
     // every cell is valid throughout and the tile lies inside the output
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
@@ -547,9 +599,20 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
       aby[k] = A.by - bj0;
       const float dy = (float)(y & (kCell - 1));
 #pragma unroll
-      for (int e = 0; e < kRun; ++e)
-        pixel_position<SORD>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy, rx[k][e],
-                             ry[k][e]);
+      for (int e = 0; e < kRun; ++e) {
+        float px, py;
+        pixel_position<SORD>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy, px, py);
+        if constexpr (INTERP == DFR_NEAREST) {
+          // a rounding decision within reach of the FP32 error: decide in FP64
+          float tx_ = px - floorf(px), ty_ = py - floorf(py);
+          if (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f) {
+            double xs, ys;
+            nearest_exact(P, xr + e, y, A.bx, A.by, px, py, xs, ys);
+          }
+        }
+        rx[k][e] = px;
+        ry[k][e] = py;
+      }
     }
     valid = ~0u;
   } else {
@@ -573,16 +636,8 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
           // a rounding decision within reach of the FP32 error: decide in FP64
           float tx_ = px - floorf(px), ty_ = py - floorf(py);
           if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
-            double xs, ys;
-            ok = position_f64(P, (double)x, (double)y, xs, ys) && fabs(xs - A.bx) < 1.0e7 &&
-                 fabs(ys - A.by) < 1.0e7;
-            if (ok) {
-              px = (float)(rint(xs) - (double)A.bx);
-              py = (float)(rint(ys) - (double)A.by);
-              exact = true;
-              dbx = xs;
-              dby = ys;
-            }
+            ok = nearest_exact(P, x, y, A.bx, A.by, px, py, dbx, dby);
+            exact = ok;
           }
         }
         rx[k][e] = px;
