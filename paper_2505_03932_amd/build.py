@@ -20,7 +20,8 @@ OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libdfr.so")
 ARCH = "gfx950"
 
-SOURCES = ["forward.hip", "batch.hip", "backward.hip", "plan.cpp", "runtime.cpp", "abi.cpp"]
+SOURCES = ["tiles_bilinear.hip", "tiles_bicubic.hip", "tiles_nearest.hip", "backward.hip",
+           "forward.hip", "batch.hip", "plan.cpp", "runtime.cpp", "abi.cpp"]
 
 CFLAGS = [
     "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-x", "hip",

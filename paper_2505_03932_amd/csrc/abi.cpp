@@ -113,7 +113,8 @@ dfr_status prepare_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_
                footprints ? footprints[i] : nullptr, plans[i]);
     max_sord = std::max(max_sord, plans[i].s_order);
   }
-  if (max_sord > 5) max_sord = 6;  // run-time order kernel
+  // run-time-order kernel for high orders and whenever the target has SIP
+  if (max_sord > 5 || plans[0].t_order > 0) max_sord = 6;
   tile = o.tile;
   if (tile == 0) {
     std::lock_guard<std::mutex> lk(tune_mutex_for_batch());
@@ -242,6 +243,10 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
   std::memset(&G, 0, sizeof(G));
   if (out_h > 0 && out_w > 0) {
     int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false, 2);
+    TileShape t4;
+    // the backward kernel runs 1 or 2 rows per thread: 4-row tiles use
+    // their 2-row sibling of the same width
+    if (tile_shape(tile, t4) && t4.np == 4) tile -= 1;
     make_geom(P, out_h, out_w, (int)interp, tile, o, G, ts, 2);
   }
   const int ns = backward_sums(P.s_order);

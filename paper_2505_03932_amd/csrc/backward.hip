@@ -95,7 +95,7 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
   }
 }
 
-template <int INTERP, int SORD, int NP>
+template <int INTERP, int SORD, int NP, bool TSIP>
 __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom G,
                                                           const float *__restrict__ gout,
                                                           float *__restrict__ gsrc,
@@ -113,9 +113,9 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
   for (int s = 0; s < NS; ++s) acc[s] = 0.0f;
 
   TileCtx c;
-  if (tile_anchors<INTERP, SORD, NP>(P, G, tile, sh, c)) {
+  if (tile_anchors<INTERP, SORD, TSIP, NP>(P, G, tile, sh, c)) {
     TilePos<NP> T;
-    tile_positions<INTERP, SORD, NP>(P, G, sh, c, T);
+    tile_positions<INTERP, SORD, TSIP, NP>(P, G, sh, c, T);
     const int bw = T.empty ? 0 : T.bi1 - T.bi0 + 1;
     const int bh = T.empty ? 0 : T.bj1 - T.bj0 + 1;
     const bool use_lds = !T.empty && 2 * (int64_t)bw * bh <= (int64_t)G.lds_cap;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
           const Anchor &A = sh.anchor[T.aidx[k]];
           PixelGeom pg;
           float px, py;
-          pixel_position<SORD>(P, A, tinv, sinv, (float)((c.xr & (kCell - 1)) + e),
+          pixel_position<SORD, TSIP>(P, A, tinv, sinv, (float)((c.xr & (kCell - 1)) + e),
                                (float)(y & (kCell - 1)), px, py, &pg);
           float fa, fau, fav, fb, fbu, fbv;
           sip_f32_grad<SORD>(P.fsA, pg.us, pg.vs, fa, fau, fav);
@@ -224,34 +224,34 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
 
 using BwdKernel = void (*)(FramePlan, TileGeom, const float *, float *, int64_t, double *);
 
-template <int INTERP, int NP>
+template <int INTERP, int NP, bool TSIP>
 static BwdKernel bwd_sord(int sord) {
   switch (sord) {
-    case 0: return reproject_bwd<INTERP, 0, NP>;
-    case 1: return reproject_bwd<INTERP, 1, NP>;
-    case 2: return reproject_bwd<INTERP, 2, NP>;
-    case 3: return reproject_bwd<INTERP, 3, NP>;
-    case 4: return reproject_bwd<INTERP, 4, NP>;
-    default: return reproject_bwd<INTERP, 5, NP>;
+    case 0: return reproject_bwd<INTERP, 0, NP, TSIP>;
+    case 1: return reproject_bwd<INTERP, 1, NP, TSIP>;
+    case 2: return reproject_bwd<INTERP, 2, NP, TSIP>;
+    case 3: return reproject_bwd<INTERP, 3, NP, TSIP>;
+    case 4: return reproject_bwd<INTERP, 4, NP, TSIP>;
+    default: return reproject_bwd<INTERP, 5, NP, TSIP>;
   }
 }
 
+// The backward kernel runs 1 or 2 rows per thread (the host picks such
+// tiles); the target SIP is compiled in only where the target has one.
 template <int INTERP>
-static BwdKernel bwd_np(int np, int sord) {
-  switch (np) {
-    case 1: return bwd_sord<INTERP, 1>(sord);
-    case 2: return bwd_sord<INTERP, 2>(sord);
-    default: return bwd_sord<INTERP, 4>(sord);
-  }
+static BwdKernel bwd_pick(int np, int sord, bool tsip) {
+  if (tsip) return np == 1 ? bwd_sord<INTERP, 1, true>(sord) : bwd_sord<INTERP, 2, true>(sord);
+  return np == 1 ? bwd_sord<INTERP, 1, false>(sord) : bwd_sord<INTERP, 2, false>(sord);
 }
 
 hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, int np,
                            const float *grad_out, float *grad_src, int64_t gsrc_pitch,
                            double *partials, hipStream_t stream) {
   if (G.n_tiles <= 0) return hipSuccess;
-  BwdKernel k = interp == DFR_NEAREST    ? bwd_np<DFR_NEAREST>(np, P.s_order)
-                : interp == DFR_BILINEAR ? bwd_np<DFR_BILINEAR>(np, P.s_order)
-                                         : bwd_np<DFR_BICUBIC>(np, P.s_order);
+  const bool tsip = P.t_order > 0;
+  BwdKernel k = interp == DFR_NEAREST    ? bwd_pick<DFR_NEAREST>(np, P.s_order, tsip)
+                : interp == DFR_BILINEAR ? bwd_pick<DFR_BILINEAR>(np, P.s_order, tsip)
+                                         : bwd_pick<DFR_BICUBIC>(np, P.s_order, tsip);
   size_t lds = (size_t)G.lds_cap * sizeof(float);
   hipLaunchKernelGGL(k, dim3(G.n_tiles), dim3(kThreads), lds, stream, P, G, grad_out, grad_src,
                      gsrc_pitch, partials);

@@ -269,12 +269,13 @@ __host__ __device__ __forceinline__ bool position_f64(const FramePlan &P, double
 }
 
 // position_f64 with the source SIP order known at compile time (when SORD
-// >= 0; the padded coefficients make it equal to the run-time version).
-template <int SORD>
+// >= 0; the padded coefficients make it equal to the run-time version);
+// the target SIP is compiled in only when TSIP.
+template <int SORD, bool TSIP>
 __device__ __forceinline__ bool position_f64_ct(const FramePlan &P, double x, double y,
                                                 double &xs, double &ys) {
   double u = x - P.tcr[0], v = y - P.tcr[1];
-  if (P.t_order > 0) {
+  if (TSIP && P.t_order > 0) {
     double du = sip_f64_dev(P.tA, P.t_order, u, v);
     double dv = sip_f64_dev(P.tB, P.t_order, u, v);
     u += du;
@@ -297,8 +298,9 @@ constexpr double kFar = 268435456.0;  // 2^28: anchors beyond this are out of an
 
 // FP64 evaluation at the anchor pixel (xa, ya) of a cell.  `support` is how
 // far interpolation taps reach beyond the position (0, 1 or 2 px).  SORD is
-// the source SIP order when known at compile time (< 0: read at run time).
-template <int SORD>
+// the source SIP order when known at compile time (< 0: read at run time);
+// TSIP compiles in the target SIP (kernels without it require t_order 0).
+template <int SORD, bool TSIP>
 __device__ __forceinline__ void compute_anchor(const FramePlan &P, int xa, int ya, int support,
                                                Anchor &A) {
   double u = (double)xa - P.tcr[0], v = (double)ya - P.tcr[1];
@@ -306,7 +308,7 @@ __device__ __forceinline__ void compute_anchor(const FramePlan &P, int xa, int y
   A.tvs = 0.0f;
   A.ta0 = 0.0f;
   A.tb0 = 0.0f;
-  if (P.t_order > 0) {
+  if (TSIP && P.t_order > 0) {
     A.tus = (float)(u * P.t_inv_scale);
     A.tvs = (float)(v * P.t_inv_scale);
     A.ta0 = sip_f32_rt(P.ftA, P.t_order, A.tus, A.tvs);

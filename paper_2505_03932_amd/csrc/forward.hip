@@ -1,57 +1,25 @@
-// Forward reprojection kernels: the FP32 tiled path (FP64 anchors, FP32
-// per-pixel offsets, LDS-staged source tiles) and the two FP64 comparison
-// forms (composed projective map; explicit two-stage trigonometry of the
-// paper's section 3.2).
-#include "forward_body.hpp"
-#include "launch.hpp"
+// Forward reprojection launchers: the FP32 tiled path (kernels in
+// tile_kernels.hpp: FP64 anchors, FP32 per-pixel offsets, LDS-staged source
+// boxes) and the two FP64 comparison forms (composed projective map;
+// explicit two-stage trigonometry of the paper's section 3.2).
+#include "tile_kernels.hpp"
 
 namespace dfr {
 
-template <int INTERP, int SORD, int NP>
-__global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(NP >= 4 ? 4 : (INTERP == DFR_BILINEAR ? 8 : 6))))
-void reproject_tiles(FramePlan P, TileGeom G) {
-  extern __shared__ float lds[];
-  __shared__ TileShared sh;
-  forward_tile<INTERP, SORD, NP>(P, G, xcd_tile(blockIdx.x, G.n_tiles), lds, sh);
-}
-
 using TileKernel = void (*)(FramePlan, TileGeom);
 
-template <int INTERP, int NP>
-static TileKernel pick_sord(int sord) {
-  switch (sord) {
-    case 0: return reproject_tiles<INTERP, 0, NP>;
-    case 1: return reproject_tiles<INTERP, 1, NP>;
-    case 2: return reproject_tiles<INTERP, 2, NP>;
-    case 3: return reproject_tiles<INTERP, 3, NP>;
-    case 4: return reproject_tiles<INTERP, 4, NP>;
-    case 5: return reproject_tiles<INTERP, 5, NP>;
-    default: return reproject_tiles<INTERP, kRtOrder, NP>;
-  }
-}
-
-template <int INTERP>
-static TileKernel pick_np(int np, int sord) {
-  switch (np) {
-    case 1: return pick_sord<INTERP, 1>(sord);
-    case 2: return pick_sord<INTERP, 2>(sord);
-    default: return pick_sord<INTERP, 4>(sord);
-  }
-}
-
 static TileKernel pick_tile_kernel(int interp, int np, int sord) {
-  switch (interp) {
-    case DFR_NEAREST: return pick_np<DFR_NEAREST>(np, sord);
-    case DFR_BILINEAR: return pick_np<DFR_BILINEAR>(np, sord);
-    default: return pick_np<DFR_BICUBIC>(np, sord);
-  }
+  const void *k = interp == DFR_NEAREST    ? tile_kernel_for<DFR_NEAREST>(np, sord)
+                  : interp == DFR_BILINEAR ? tile_kernel_for<DFR_BILINEAR>(np, sord)
+                                           : tile_kernel_for<DFR_BICUBIC>(np, sord);
+  return reinterpret_cast<TileKernel>(const_cast<void *>(k));
 }
 
 hipError_t launch_forward_f32(const FramePlan &P, const TileGeom &G, int interp, int np,
                               hipStream_t stream) {
   if (G.n_tiles <= 0) return hipSuccess;
-  TileKernel k = pick_tile_kernel(interp, np, P.s_order);
+  // a target with SIP A/B needs the kernel that compiles the target SIP in
+  TileKernel k = pick_tile_kernel(interp, np, P.t_order > 0 ? kRtOrder : P.s_order);
   size_t lds = (size_t)G.lds_cap * sizeof(float);
   hipLaunchKernelGGL(k, dim3(G.n_tiles), dim3(kThreads), lds, stream, P, G);
   return hipGetLastError();
@@ -178,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void reproject_f64(FramePlan P, TrigPlan 
        idx += (int64_t)gridDim.x * kThreads) {
     const int y = (int)(idx / G.out_w), x = (int)(idx - (int64_t)y * G.out_w);
     double xs = 0.0, ys = 0.0;
-    bool ok = TRIG ? position_trig(P, T, x, y, xs, ys) : position_f64_ct<kRtOrder>(P, x, y, xs, ys);
+    bool ok = TRIG ? position_trig(P, T, x, y, xs, ys) : position_f64_ct<kRtOrder, true>(P, x, y, xs, ys);
     ok = ok && fabs(xs) < 4.0e15 && fabs(ys) < 4.0e15;
     double o = 0.0, f = 0.0;
     if (ok && P.src_h > 0 && P.src_w > 0) interp_f64<INTERP>(P, xs, ys, (double)G.cubic_a, o, f);

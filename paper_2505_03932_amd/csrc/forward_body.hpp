@@ -40,13 +40,13 @@ struct PixelGeom {
 
 // FP32 source position of the pixel at offset (dx, dy) from its anchor,
 // relative to (A.bx, A.by).  Returns false for directions on or behind the
-// source tangent plane.
-template <int SORD>
+// source tangent plane.  TSIP compiles in the target SIP.
+template <int SORD, bool TSIP>
 __device__ __forceinline__ bool pixel_position(const FramePlan &P, const Anchor &A, float tinv,
                                                float sinv, float dx, float dy, float &rx,
                                                float &ry, PixelGeom *geom = nullptr) {
   float du = dx, dv = dy;
-  if (P.t_order > 0) {
+  if (TSIP && P.t_order > 0) {
     float us = fmaf(dx, tinv, A.tus), vs = fmaf(dy, tinv, A.tvs);
     du = dx + (sip_f32_rt(P.ftA, P.t_order, us, vs) - A.ta0);
     dv = dy + (sip_f32_rt(P.ftB, P.t_order, us, vs) - A.tb0);
@@ -80,7 +80,7 @@ struct TileShared {
   int touch;      // any anchor cell can reach the source
   int item;       // batch: work item handed to this work-group
   int cells_ok;   // forward: every anchor cell has valid positions throughout
-  int box_ok;     // forward: the 9 box samples are all valid
+  int box_ok;     // forward: the anchors' linear models give a usable box
 };
 
 template <int INTERP>
@@ -101,7 +101,7 @@ struct TileCtx {
 
 // Phase 1.  Returns false when no pixel of the tile can reach the source
 // (and skipping is allowed): the caller then only writes "uncovered".
-template <int INTERP, int SORD, int NP>
+template <int INTERP, int SORD, bool TSIP, int NP>
 __device__ __forceinline__ bool tile_anchors(const FramePlan &P, const TileGeom &G, int tile,
                                              TileShared &sh, TileCtx &c) {
   const int tid = threadIdx.x;
@@ -123,7 +123,7 @@ __device__ __forceinline__ bool tile_anchors(const FramePlan &P, const TileGeom 
     int t = 0;
     if (tid < nA) {
       int cy = c.cy0 + tid / c.ncx, cx = c.cx0 + tid % c.ncx;
-      compute_anchor<SORD>(P, cx * kCell, cy * kCell, TapSupport<INTERP>::hi, sh.anchor[tid]);
+      compute_anchor<SORD, TSIP>(P, cx * kCell, cy * kCell, TapSupport<INTERP>::hi, sh.anchor[tid]);
       t = sh.anchor[tid].touch;
     }
     unsigned long long any = __ballot(t != 0);
@@ -150,7 +150,7 @@ struct TilePos {
 };
 
 // Phases 2 and 3 (ends with a barrier; the box is then known to all).
-template <int INTERP, int SORD, int NP>
+template <int INTERP, int SORD, bool TSIP, int NP>
 __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeom &G,
                                                TileShared &sh, const TileCtx &c,
                                                TilePos<NP> &T) {
@@ -173,7 +173,7 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
       const int x = c.xr + e;
       const float dx = (float)((c.xr & (kCell - 1)) + e);
       float px, py;
-      bool ok = pixel_position<SORD>(P, A, tinv, sinv, dx, dy, px, py);
+      bool ok = pixel_position<SORD, TSIP>(P, A, tinv, sinv, dx, dy, px, py);
       ok = ok && (y < G.out_h) && (x < G.out_w);
       double dbx = 0.0, dby = 0.0;
       bool exact = false;
@@ -182,7 +182,7 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
         float tx_ = px - floorf(px), ty_ = py - floorf(py);
         if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
           double xs, ys;
-          ok = position_f64_ct<SORD>(P, (double)x, (double)y, xs, ys) && fabs(xs - A.bx) < 1.0e7 &&
+          ok = position_f64_ct<SORD, TSIP>(P, (double)x, (double)y, xs, ys) && fabs(xs - A.bx) < 1.0e7 &&
                fabs(ys - A.by) < 1.0e7;
           if (ok) {
             px = (float)(rint(xs) - (double)A.bx);
@@ -281,10 +281,11 @@ __device__ __forceinline__ bool vector_stores_ok(const FramePlan &P, const TileG
 // Nearest: the FP64 rounding decision for a pixel whose FP32 position lies
 // within 1e-4 px of a tie (rare).  Writes the rounded position relative to
 // (bx, by); returns false if the pixel has no source position.
+template <int SORD, bool TSIP>
 __device__ __forceinline__ bool nearest_exact(const FramePlan &P, int x, int y, int bx,
                                                        int by, float &px, float &py,
                                                        double &xs, double &ys) {
-  bool ok = position_f64_ct<kRtOrder>(P, (double)x, (double)y, xs, ys) && fabs(xs - bx) < 1.0e7 &&
+  bool ok = position_f64_ct<SORD, TSIP>(P, (double)x, (double)y, xs, ys) && fabs(xs - bx) < 1.0e7 &&
             fabs(ys - by) < 1.0e7;
   if (ok) {
     px = (float)(rint(xs) - (double)bx);
@@ -429,44 +430,6 @@ __device__ __forceinline__ void tap_origin(float r, int base, int &i0, float &t)
   }
 }
 
-// Wave 1 of phase 1: FP64 positions at 9 points of the tile's rectangle
-// (clipped to the output), their bounding box grown by the tap support and
-// 2 px, and whether all 9 are valid.
-template <int INTERP, int SORD>
-__device__ __forceinline__ void tile_box_samples(const FramePlan &P, const TileGeom &G, int x0,
-                                                 int y0, int TW, int TH, TileShared &sh) {
-  const int lane = threadIdx.x & 63;
-  const int xe = min(x0 + TW, G.out_w) - 1, ye = min(y0 + TH, G.out_h) - 1;
-  bool ok = true;
-  int imn = 0x3fffffff, imx = -0x3fffffff, jmn = 0x3fffffff, jmx = -0x3fffffff;
-  if (lane < 9) {
-    const int ix = lane % 3, iy = lane / 3;
-    const double px = ix == 0 ? x0 : (ix == 1 ? 0.5 * (x0 + xe) : (double)xe);
-    const double py = iy == 0 ? y0 : (iy == 1 ? 0.5 * (y0 + ye) : (double)ye);
-    double xs, ys;
-    ok = position_f64_ct<SORD>(P, px, py, xs, ys) && fabs(xs) < 1.0e9 && fabs(ys) < 1.0e9;
-    if (ok) {
-      imn = (int)floor(xs);
-      imx = imn;
-      jmn = (int)floor(ys);
-      jmx = jmn;
-    }
-  }
-  imn = wave_min(imn);
-  imx = wave_max(imx);
-  jmn = wave_min(jmn);
-  jmx = wave_max(jmx);
-  const unsigned long long bad = __ballot(!ok);
-  if (lane == 0) {
-    constexpr int lo = TapSupport<INTERP>::lo + 2, hi = TapSupport<INTERP>::hi + 2;
-    sh.box[0] = imn - lo;
-    sh.box[1] = imx + hi;
-    sh.box[2] = jmn - lo;
-    sh.box[3] = jmx + hi;
-    sh.box_ok = bad == 0ull;
-  }
-}
-
 // Stage rows [bj0, bj0+bh) x columns [bi0, bi0+bw) of the source into LDS
 // (row stride bw) with asynchronous DMA: one wave per row, 64 columns per
 // instruction, lanes past the row end masked off.
@@ -485,9 +448,12 @@ __device__ __forceinline__ void dma_box(const FramePlan &P, int bi0, int bj0, in
   }
 }
 
+// The target SIP is compiled only into the run-time-order variant (the
+// launcher uses it whenever the target WCS has A/B).
 template <int INTERP, int SORD, int NP>
 __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom &G, int tile,
                                              float *__restrict__ lds, TileShared &sh) {
+  constexpr bool TSIP = SORD == kRtOrder;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int lg = G.txt_log2;
   const int TW = kRun << lg, RP = kThreads >> lg, TH = RP * NP;
@@ -507,7 +473,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
       const int cy = cy0 + tid / ncx, cx = cx0 + tid % ncx;
       const int xa = cx * kCell, ya = cy * kCell;
       Anchor &A = sh.anchor[tid];
-      compute_anchor<SORD>(P, xa, ya, TapSupport<INTERP>::hi, A);
+      compute_anchor<SORD, TSIP>(P, xa, ya, TapSupport<INTERP>::hi, A);
       t = A.touch;
       okc = A.ok;
       // the part of the cell inside the tile and the output, as offsets
@@ -601,13 +567,13 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
 #pragma unroll
       for (int e = 0; e < kRun; ++e) {
         float px, py;
-        pixel_position<SORD>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy, px, py);
+        pixel_position<SORD, TSIP>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy, px, py);
         if constexpr (INTERP == DFR_NEAREST) {
           // a rounding decision within reach of the FP32 error: decide in FP64
           float tx_ = px - floorf(px), ty_ = py - floorf(py);
           if (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f) {
             double xs, ys;
-            nearest_exact(P, xr + e, y, A.bx, A.by, px, py, xs, ys);
+            nearest_exact<SORD, TSIP>(P, xr + e, y, A.bx, A.by, px, py, xs, ys);
           }
         }
         rx[k][e] = px;
@@ -627,7 +593,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
       for (int e = 0; e < kRun; ++e) {
         const int x = xr + e;
         float px, py;
-        bool ok = pixel_position<SORD>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy,
+        bool ok = pixel_position<SORD, TSIP>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy,
                                        px, py);
         ok = ok && (y < G.out_h) && (x < G.out_w);
         double dbx = 0.0, dby = 0.0;
@@ -636,7 +602,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
           // a rounding decision within reach of the FP32 error: decide in FP64
           float tx_ = px - floorf(px), ty_ = py - floorf(py);
           if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
-            ok = nearest_exact(P, x, y, A.bx, A.by, px, py, dbx, dby);
+            ok = nearest_exact<SORD, TSIP>(P, x, y, A.bx, A.by, px, py, dbx, dby);
             exact = ok;
           }
         }

@@ -1,0 +1,101 @@
+// The tiled forward kernels (single image and persistent batch) as
+// templates; each interpolation is instantiated in its own translation unit
+// (tiles_nearest.hip, tiles_bilinear.hip, tiles_bicubic.hip) so the library
+// builds in parallel.
+#pragma once
+
+#include "forward_body.hpp"
+#include "launch.hpp"
+
+namespace dfr {
+
+template <int INTERP, int SORD, int NP>
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(NP >= 4 ? 4 : (INTERP == DFR_BILINEAR ? 8 : 6))))
+void reproject_tiles(FramePlan P, TileGeom G) {
+  extern __shared__ float lds[];
+  __shared__ TileShared sh;
+  forward_tile<INTERP, SORD, NP>(P, G, xcd_tile(blockIdx.x, G.n_tiles), lds, sh);
+}
+
+// Batched reprojection: many source frames of uneven sizes onto one target
+// grid in one persistent launch (the paper's stacking use case, section 1).
+// Work items are (frame, tile) pairs handed out by an atomic counter, so
+// frames of very different coverage balance across the whole chip; each
+// item runs exactly the single-image tile body, so every frame's result is
+// bit-identical to a single-image call.
+template <int INTERP, int SORD, int NP>
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(NP >= 4 ? 4 : 5)))
+void reproject_batch(const FramePlan *__restrict__ plans, int n_frames, TileGeom G,
+                     int *__restrict__ counter) {
+  extern __shared__ float lds[];
+  __shared__ TileShared sh;
+  const int total = n_frames * G.n_tiles;
+  while (true) {
+    if (threadIdx.x == 0) sh.item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(sh.item);
+    if (item >= total) break;  // every wave sees the same item: the group leaves together
+    const int frame = item / G.n_tiles;
+    // read the frame table through the constant address space: it is not
+    // written during the launch, so its fields can be scalar (SGPR) loads
+    using ConstPlan = const __attribute__((address_space(4))) FramePlan;
+    ConstPlan *cp = reinterpret_cast<ConstPlan *>(reinterpret_cast<uintptr_t>(plans)) + frame;
+    forward_tile<INTERP, SORD, NP>(*reinterpret_cast<const FramePlan *>(cp), G,
+                                   item - frame * G.n_tiles, lds, sh);
+    __syncthreads();
+  }
+}
+
+// Source SIP orders 0..5 have compile-time kernels; higher orders, and any
+// target with SIP A/B (sord < 0 here), use the run-time-order kernel.
+template <template <int, int, int> class K, int INTERP, int NP>
+const void *pick_sord(int sord) {
+  switch (sord) {
+    case 0: return K<INTERP, 0, NP>::ptr();
+    case 1: return K<INTERP, 1, NP>::ptr();
+    case 2: return K<INTERP, 2, NP>::ptr();
+    case 3: return K<INTERP, 3, NP>::ptr();
+    case 4: return K<INTERP, 4, NP>::ptr();
+    case 5: return K<INTERP, 5, NP>::ptr();
+    default: return K<INTERP, kRtOrder, NP>::ptr();
+  }
+}
+
+template <int INTERP, int SORD, int NP>
+struct TileK {
+  static const void *ptr() { return reinterpret_cast<const void *>(reproject_tiles<INTERP, SORD, NP>); }
+};
+template <int INTERP, int SORD, int NP>
+struct BatchK {
+  static const void *ptr() { return reinterpret_cast<const void *>(reproject_batch<INTERP, SORD, NP>); }
+};
+
+// Kernel for (rows per thread, source SIP order) of one interpolation.
+template <int INTERP>
+const void *tile_kernel_for(int np, int sord) {
+  switch (np) {
+    case 1: return pick_sord<TileK, INTERP, 1>(sord);
+    case 2: return pick_sord<TileK, INTERP, 2>(sord);
+    default: return pick_sord<TileK, INTERP, 4>(sord);
+  }
+}
+
+template <int INTERP>
+const void *batch_kernel_for(int np, int sord) {
+  switch (np) {
+    case 1: return pick_sord<BatchK, INTERP, 1>(sord);
+    case 2: return pick_sord<BatchK, INTERP, 2>(sord);
+    default: return pick_sord<BatchK, INTERP, 4>(sord);
+  }
+}
+
+extern template const void *tile_kernel_for<DFR_NEAREST>(int, int);
+extern template const void *tile_kernel_for<DFR_BILINEAR>(int, int);
+extern template const void *tile_kernel_for<DFR_BICUBIC>(int, int);
+extern template const void *batch_kernel_for<DFR_NEAREST>(int, int);
+extern template const void *batch_kernel_for<DFR_BILINEAR>(int, int);
+extern template const void *batch_kernel_for<DFR_BICUBIC>(int, int);
+
+}  // namespace dfr

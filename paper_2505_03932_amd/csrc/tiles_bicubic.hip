@@ -1,0 +1,7 @@
+// Tiled forward and batch kernels, bicubic interpolation.
+#include "tile_kernels.hpp"
+
+namespace dfr {
+template const void *tile_kernel_for<DFR_BICUBIC>(int, int);
+template const void *batch_kernel_for<DFR_BICUBIC>(int, int);
+}  // namespace dfr

@@ -1,0 +1,7 @@
+// Tiled forward and batch kernels, bilinear interpolation.
+#include "tile_kernels.hpp"
+
+namespace dfr {
+template const void *tile_kernel_for<DFR_BILINEAR>(int, int);
+template const void *batch_kernel_for<DFR_BILINEAR>(int, int);
+}  // namespace dfr
