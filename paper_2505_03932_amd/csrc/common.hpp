@@ -60,7 +60,8 @@ struct FramePlan {
   float *fp;                // device [out_h][out_w] or null
   int32_t t_order;          // target A/B order (0 = none)
   int32_t s_order;          // source AP/BP order (0 = none)
-  int32_t pad_[2];
+  int32_t series;           // 1: |k.d| < 1e-3 over the frame, 1/(1+e) = 1 - e + e^2
+  int32_t pad_;
   double tA[kMaxCoef], tB[kMaxCoef];   // FP64 coefficients, packed by tri9
   double sA[kMaxCoef], sB[kMaxCoef];
   float ftA[kMaxCoef], ftB[kMaxCoef];  // FP32, scaled: c * S^(p+q)
@@ -94,6 +95,7 @@ struct alignas(16) Anchor {
   int32_t ok;                    // every pixel of the cell has a valid, finite position
   float jx[2], jy[2];            // d(source position)/d(target pixel) at the anchor
   float sx0, sy0;                // source position at the anchor minus (bx, by)
+  float ex, ey;                  // bound on |position - linear model| over the cell
 };
 
 // ------------------------------------------------------ SIP polynomials --
@@ -296,6 +298,26 @@ __device__ __forceinline__ bool position_f64_ct(const FramePlan &P, double x, do
 
 constexpr double kFar = 268435456.0;  // 2^28: anchors beyond this are out of any image
 
+// Sum over the terms of order >= 2 of |c| (p+q)(p+q-1) R^(p+q-2): bounds
+// every second partial derivative of the polynomial on [-R, R]^2.
+template <int SORD>
+__device__ __forceinline__ float sip_hess_bound(const float *__restrict__ c, int n, float R) {
+  constexpr int N = SORD >= 0 ? SORD : kMaxOrder;
+  float b = 0.0f;
+#pragma unroll
+  for (int p = 0; p <= N; ++p)
+#pragma unroll
+    for (int q = 0; p + q <= N; ++q) {
+      const int m = p + q;
+      if (m < 2 || (SORD < 0 && m > n)) continue;
+      float rp = 1.0f;
+#pragma unroll
+      for (int i = 0; i < m - 2; ++i) rp *= R;
+      b = fmaf(fabsf(c[tri9(p, q)]) * (float)(m * (m - 1)), rp, b);
+    }
+  return b;
+}
+
 // FP64 evaluation at the anchor pixel (xa, ya) of a cell.  `support` is how
 // far interpolation taps reach beyond the position (0, 1 or 2 px).  SORD is
 // the source SIP order when known at compile time (< 0: read at run time);
@@ -382,6 +404,28 @@ __device__ __forceinline__ void compute_anchor(const FramePlan &P, int xa, int y
     A.jy[1] = bpu * A.g2 + (1.0f + bpv) * A.f2;
     A.sx0 = A.c0x + fa;
     A.sy0 = A.c0y + fb;
+    // Rigorous distance of the cell's positions from that linear model:
+    //  - projective denominator: |dU - g.d| <= |g.d| kap / (1 - kap),
+    //    kap = max |k.d| over the cell;
+    //  - SIP: second-order Taylor remainder, 1/2 B (|dU| + |dV|)^2 with B a
+    //    bound on the second derivatives over the cell (scaled units);
+    //  - 0.05 px for FP32 rounding of positions and of this bound.
+    const float span = (float)(kCell - 1);
+    const float kap = (fabsf(A.k1) + fabsf(A.k2)) * span;
+    if (kap < 0.5f) {
+      const float gu = (fabsf(A.g1) + fabsf(A.g2)) * span, gv = (fabsf(A.f1) + fabsf(A.f2)) * span;
+      const float du_max = gu / (1.0f - kap), dv_max = gv / (1.0f - kap);
+      const float eu = gu * kap / (1.0f - kap), ev = gv * kap / (1.0f - kap);
+      const float R = fmaxf(fabsf(A.u0s), fabsf(A.v0s)) + (du_max + dv_max) * s_;
+      const float d2 = (du_max + dv_max) * s_;
+      const float r2a = 0.5f * sip_hess_bound<SORD>(P.fsA, P.s_order, R) * d2 * d2;
+      const float r2b = 0.5f * sip_hess_bound<SORD>(P.fsB, P.s_order, R) * d2 * d2;
+      A.ex = (1.0f + fabsf(apu)) * eu + fabsf(apv) * ev + r2a + 0.05f;
+      A.ey = fabsf(bpu) * eu + (1.0f + fabsf(bpv)) * ev + r2b + 0.05f;
+    } else {
+      A.ex = 1.0e30f;
+      A.ey = 1.0e30f;
+    }
   }
   double kk = (fabs(H[6]) + fabs(H[7])) * fabs(iw) * 2.0 * kCell;
   // w > 0 at the anchor and |k . d| < 1/4 over the cell: w > 0 at every pixel

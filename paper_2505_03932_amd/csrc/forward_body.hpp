@@ -51,10 +51,18 @@ __device__ __forceinline__ bool pixel_position(const FramePlan &P, const Anchor 
     du = dx + (sip_f32_rt(P.ftA, P.t_order, us, vs) - A.ta0);
     dv = dy + (sip_f32_rt(P.ftB, P.t_order, us, vs) - A.tb0);
   }
-  float den = fmaf(A.k1, du, fmaf(A.k2, dv, 1.0f));
   float nu = fmaf(A.g1, du, A.g2 * dv);
   float nv = fmaf(A.f1, du, A.f2 * dv);
-  float r = __builtin_amdgcn_rcpf(den);
+  float den, r;
+  if (P.series) {
+    // |e| < 1e-3: 1/(1+e) = 1 - e + e^2 to a relative 1e-9
+    const float e = fmaf(A.k1, du, A.k2 * dv);
+    den = 1.0f + e;
+    r = fmaf(e, e - 1.0f, 1.0f);
+  } else {
+    den = fmaf(A.k1, du, fmaf(A.k2, dv, 1.0f));
+    r = __builtin_amdgcn_rcpf(den);
+  }
   float dU = nu * r, dV = nv * r;
   float us = fmaf(dU, sinv, A.u0s), vs = fmaf(dV, sinv, A.v0s);
   float ax = sip_src<SORD>(P.fsA, P.s_order, us, vs);
@@ -480,12 +488,9 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
       const float ux = (float)(min(xa + kCell, min(x0 + TW, G.out_w)) - 1 - xa);
       const float vy0 = (float)(max(ya, y0) - ya);
       const float vy1 = (float)(min(ya + kCell, min(y0 + TH, G.out_h)) - 1 - ya);
-      // extremes of the linear model over that rectangle (+ curvature slack
-      // from the projective denominator), relative to (bx, by)
-      const float curv = (fabsf(A.k1) + fabsf(A.k2)) * (float)kCell;
-      const float ex = fabsf(A.jx[0]) * ux + fabsf(A.jx[1]) * fmaxf(vy1, 0.0f);
-      const float ey = fabsf(A.jy[0]) * ux + fabsf(A.jy[1]) * fmaxf(vy1, 0.0f);
-      const float mx = ex * curv, my = ey * curv;
+      // extremes of the linear model over that rectangle, grown by the
+      // rigorous bound on the model's error, relative to (bx, by)
+      const float mx = A.ex, my = A.ey;
       const float x_a = A.sx0 + fminf(0.0f, A.jx[0] * ux) + fminf(A.jx[1] * vy0, A.jx[1] * vy1) - mx;
       const float x_b = A.sx0 + fmaxf(0.0f, A.jx[0] * ux) + fmaxf(A.jx[1] * vy0, A.jx[1] * vy1) + mx;
       const float y_a = A.sy0 + fminf(0.0f, A.jy[0] * ux) + fminf(A.jy[1] * vy0, A.jy[1] * vy1) - my;
@@ -631,30 +636,13 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   constexpr int SPAN = TapSupport<INTERP>::lo + TapSupport<INTERP>::hi;
-  // Fast path: every tap of every pixel inside the staged box.  With
-  // b = box-relative anchor base, floor(r) + b - lo must lie in
-  // [0, extent - 1 - SPAN]: r in [lo - b, extent - SPAN + lo - b) (rint:
-  // shifted by one half).
-  bool fast = interior && valid == ~0u;
-  if (fast) {
-    constexpr float half = INTERP == DFR_NEAREST ? 0.5f : 0.0f;
-    bool inside = true;
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const float lx = (float)(TapSupport<INTERP>::lo - abx[k]) - half;
-      const float hx = (float)(bw - SPAN + TapSupport<INTERP>::lo - abx[k]) - half;
-      const float ly = (float)(TapSupport<INTERP>::lo - aby[k]) - half;
-      const float hy = (float)(bh - SPAN + TapSupport<INTERP>::lo - aby[k]) - half;
-#pragma unroll
-      for (int e = 0; e < kRun; ++e)
-        inside = inside && rx[k][e] >= lx && rx[k][e] < hx && ry[k][e] >= ly && ry[k][e] < hy;
-    }
-    fast = __ballot(!inside) == 0ull;
-  }
+  // Interior tiles need no per-pixel check: the box holds every tap by the
+  // rigorous margin of the anchors' linear models.
+  const bool fast = interior && valid == ~0u;
   const float a = G.cubic_a;
   if (fast) {
-    // box-relative tap coordinates: unmasked LDS reads, footprint exactly 1
-    auto fl = [&](int i, int j) -> float { return lds[__umul24(j, bw) + i]; };
+    // box-relative tap coordinates: unmasked LDS reads from one base address
+    // per pixel, footprint exactly 1
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
       const int y = y0 + ty + k * RP;
@@ -665,15 +653,18 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
         float t_, s_;
         tap_origin<INTERP>(rx[k][e], abx[k], i0, t_);
         tap_origin<INTERP>(ry[k][e], aby[k], j0, s_);
+        // i0, j0 >= 0 inside the box: one 24-bit multiply-add per pixel
+        const float *__restrict__ b = lds + __umul24(j0, bw) + i0;
+        auto fl = [&](int i, int j) -> float { return b[j * bw + i]; };
         if constexpr (INTERP == DFR_NEAREST) {
-          o[e] = fl(i0, j0);
+          o[e] = b[0];
         } else if constexpr (INTERP == DFR_BILINEAR) {
-          o[e] = Taps<DFR_BILINEAR>::interior(i0, j0, t_, s_, fl);
+          o[e] = Taps<DFR_BILINEAR>::interior(0, 0, t_, s_, fl);
         } else {
           float wx[4], wy[4];
           keys_weights(t_, a, wx);
           keys_weights(s_, a, wy);
-          o[e] = Taps<DFR_BICUBIC>::interior(i0, j0, wx, wy, fl);
+          o[e] = Taps<DFR_BICUBIC>::interior(0, 0, wx, wy, fl);
         }
         f[e] = 1.0f;
       }

@@ -159,6 +159,24 @@ void build_plan(const float *src, int32_t src_h, int32_t src_w, int64_t pitch,
   scale_pack(P.tB, St, P.ftB);
   scale_pack(P.sA, Ss, P.fsA);
   scale_pack(P.sB, Ss, P.fsB);
+  // The projective denominator over a cell is 1 + e with |e| <= (|H20| +
+  // |H21|) * 31 / w.  w is linear in the target offset, so its minimum over
+  // the output frame (grown by a margin for target SIP) is at a corner.  When
+  // |e| < 1e-3 everywhere, 1/(1+e) is evaluated as 1 - e + e^2 (relative
+  // error below 1e-9) instead of a reciprocal instruction.
+  {
+    double mg = 64.0 + 0.1 * std::max(out_h, out_w);
+    double wmin = 1e300;
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        double u = (cx ? out_w - 1 + mg : -mg) - P.tcr[0];
+        double v = (cy ? out_h - 1 + mg : -mg) - P.tcr[1];
+        wmin = std::min(wmin, P.H[6] * u + P.H[7] * v + P.H[8]);
+      }
+    double kap = wmin > 0.0 ? 1.2 * (std::fabs(P.H[6]) + std::fabs(P.H[7])) * (kCell - 1) / wmin
+                            : 1e300;
+    P.series = kap < 1e-3 ? 1 : 0;
+  }
 }
 
 void build_trig_plan(const dfr_wcs &sw, const dfr_wcs &tw, TrigPlan &T) {

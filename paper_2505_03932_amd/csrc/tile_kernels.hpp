@@ -41,9 +41,9 @@ void reproject_batch(const FramePlan *__restrict__ plans, int n_frames, TileGeom
     // read the frame table through the constant address space: it is not
     // written during the launch, so its fields can be scalar (SGPR) loads
     using ConstPlan = const __attribute__((address_space(4))) FramePlan;
-    ConstPlan *cp = reinterpret_cast<ConstPlan *>(reinterpret_cast<uintptr_t>(plans)) + frame;
-    forward_tile<INTERP, SORD, NP>(*reinterpret_cast<const FramePlan *>(cp), G,
-                                   item - frame * G.n_tiles, lds, sh);
+    ConstPlan *cp = (ConstPlan *)(plans + frame);
+    forward_tile<INTERP, SORD, NP>(*(const FramePlan *)cp, G, item - frame * G.n_tiles, lds,
+                                   sh);
     __syncthreads();
   }
 }
