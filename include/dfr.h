@@ -79,10 +79,14 @@ typedef enum {
 } dfr_status;
 
 typedef enum {
-  DFR_PREC_F32 = 0,      /* FP64 per-anchor set-up, FP32 per-pixel offsets (default) */
+  DFR_PREC_F32 = 0,      /* FP64 set-up per 32x32 cell, FP32 per pixel (default): a
+                            certified cubic model of the cell's position map where
+                            its bound holds (target without SIP), else the full
+                            chain as FP32 offsets from an FP64 anchor              */
   DFR_PREC_F64 = 1,      /* every pixel in FP64 through the composed rotation        */
-  DFR_PREC_TRIG_F64 = 2  /* every pixel in FP64 through explicit (RA, Dec) and the
+  DFR_PREC_TRIG_F64 = 2, /* every pixel in FP64 through explicit (RA, Dec) and the
                             trigonometric two-stage form of section 3.2              */
+  DFR_PREC_F32_ANCHOR = 3 /* FP32 per pixel, always the full chain from anchors    */
 } dfr_precision;
 
 typedef struct dfr_options {
@@ -184,6 +188,26 @@ void dfr_cd_from_pc_cdelt(const double pc[4], const double cdelt[2], double cd[4
 
 /* Validate a WCS the way every entry point does (host only, no device). */
 dfr_status dfr_check_wcs(const dfr_wcs *wcs, int32_t as_source);
+
+/* The local position model of one 32x32 cell of output pixels that the
+ * default FP32 path evaluates (section 3.2's two stages composed; host only,
+ * no device work).  Cell (cx, cy) holds output pixels x in [32 cx, 32 cx+32),
+ * y in [32 cy, 32 cy+32); a pixel's offsets from the cell centre are
+ * a = x - (32 cx + 15.5), b = y - (32 cy + 15.5), and the model is
+ *   x_src = base[0] + sum_k coef_x[k] a^i b^j   (y_src likewise)
+ * with (i, j) for k = 0..9: (0,0) (0,1) (0,2) (0,3) (1,0) (1,1) (1,2) (2,0)
+ * (2,1) (3,0); the coefficients are the FP32 values the kernels use.
+ * `bound` receives a rigorous bound (px) on |model - exact position| over the
+ * whole cell (1e30 where no model exists: a target with SIP, a projective
+ * denominator that may vanish in the cell), `certified` 1 when the kernels
+ * use the model: the part of the bound the cubic leaves out of the map is
+ * <= 1e-6 px (the rest is the FP32 rounding of the coefficients, about
+ * 6e-8 of their contributions, which the FP32 chain shares).  All outputs are host pointers and may
+ * be NULL.  Errors: DFR_E_NULL (a WCS is NULL), DFR_E_WCS /
+ * DFR_E_UNSUPPORTED as dfr_reproject, DFR_E_ARG (cx or cy negative). */
+dfr_status dfr_cell_model(const dfr_wcs *src_wcs, const dfr_wcs *tgt_wcs, int32_t cx, int32_t cy,
+                          double coef_x[10], double coef_y[10], int32_t base[2], double *bound,
+                          int32_t *certified);
 
 /* Free cached per-device workspaces and graphs (the calling thread's device). */
 dfr_status dfr_release(void);

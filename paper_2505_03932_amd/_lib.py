@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libdfr.so")
 
 DFR_MAX_SIP_ORDER = 9
 DFR_NEAREST, DFR_BILINEAR, DFR_BICUBIC = 0, 1, 2
-DFR_PREC_F32, DFR_PREC_F64, DFR_PREC_TRIG_F64 = 0, 1, 2
+DFR_PREC_F32, DFR_PREC_F64, DFR_PREC_TRIG_F64, DFR_PREC_F32_ANCHOR = 0, 1, 2, 3
 DFR_OK = 0
 STATUS_NAMES = {0: "DFR_OK", 1: "DFR_E_NULL", 2: "DFR_E_SHAPE", 3: "DFR_E_WCS",
                 4: "DFR_E_UNSUPPORTED", 5: "DFR_E_DEVICE", 6: "DFR_E_NOMEM", 7: "DFR_E_ARG"}
@@ -24,7 +24,7 @@ EXPORTED = [
     "dfr_options_init", "dfr_reproject", "dfr_reproject_batch", "dfr_wcs_grad_size",
     "dfr_reproject_backward", "dfr_sq_residual", "dfr_autotune", "dfr_autotune_batch",
     "dfr_tile_count", "dfr_tile_shape", "dfr_cd_from_pc_cdelt", "dfr_check_wcs",
-    "dfr_release", "dfr_strerror", "dfr_abi_version",
+    "dfr_cell_model", "dfr_release", "dfr_strerror", "dfr_abi_version",
 ]
 
 
@@ -57,6 +57,15 @@ def _load():
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_2505_03932_amd.build` "
             "(hipcc, gfx950).  There is no fallback implementation.")
+    # libdfr needs libamdhip64.so.7, and torch ships its own copy under the
+    # same soname: whichever is loaded first serves both.  Loading torch
+    # first makes the library run on torch's HIP runtime, so torch's streams
+    # and device pointers are valid in it (the other order leaves torch and
+    # libdfr on different runtime instances).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, st = C.c_void_p, C.c_int32, C.c_int64, C.c_int
     W = C.POINTER(dfr_wcs)
@@ -88,6 +97,9 @@ def _load():
     L.dfr_cd_from_pc_cdelt.restype = None
     L.dfr_check_wcs.argtypes = [W, i32]
     L.dfr_check_wcs.restype = st
+    D = C.POINTER(C.c_double)
+    L.dfr_cell_model.argtypes = [W, W, i32, i32, D, D, C.POINTER(i32), D, C.POINTER(i32)]
+    L.dfr_cell_model.restype = st
     L.dfr_release.argtypes = []
     L.dfr_release.restype = st
     L.dfr_strerror.argtypes = [st]
@@ -171,6 +183,16 @@ def dfr_cd_from_pc_cdelt(pc, cdelt):
 
 def dfr_check_wcs(wcs, as_source: bool) -> int:
     return lib.dfr_check_wcs(C.byref(wcs), 1 if as_source else 0)
+
+
+def dfr_cell_model(src_wcs, tgt_wcs, cx: int, cy: int):
+    """Returns (status, coef_x[10], coef_y[10], (base_x, base_y), bound, certified)."""
+    cxs, cys = (C.c_double * 10)(), (C.c_double * 10)()
+    base = (C.c_int32 * 2)()
+    bound, cert = C.c_double(0.0), C.c_int32(0)
+    s = lib.dfr_cell_model(C.byref(src_wcs), C.byref(tgt_wcs), cx, cy, cxs, cys, base,
+                           C.byref(bound), C.byref(cert))
+    return s, list(cxs), list(cys), (base[0], base[1]), bound.value, cert.value
 
 
 def dfr_release() -> int:

@@ -27,7 +27,8 @@ from ._lib import DfrError
 
 ORDERS = {"nearest": 0, "nearest-neighbor": 0, "nearest_neighbor": 0, "bilinear": 1,
           "bicubic": 2, 0: 0, 1: 1, 2: 2}
-PRECISIONS = {"f32": 0, "fp32": 0, "f64": 1, "fp64": 1, "trig": 2, "trig_f64": 2, 0: 0, 1: 1, 2: 2}
+PRECISIONS = {"f32": 0, "fp32": 0, "f64": 1, "fp64": 1, "trig": 2, "trig_f64": 2,
+              "f32_anchor": 3, 0: 0, 1: 1, 2: 2, 3: 3}
 
 
 @dataclass
@@ -325,6 +326,16 @@ def sq_residual(out, ref, mask=None, want_grad=True):
                              _ptr(g), _stream(out.device))
     _check(s, "dfr_sq_residual")
     return loss, g
+
+
+def cell_model(src_wcs, tgt_wcs, cx: int, cy: int) -> dict:
+    """The local position model of output cell (cx, cy) the default FP32 path
+    evaluates (host only): FP32 coefficients, integer base, certified bound."""
+    s, mx, my, base, bound, cert = _lib.dfr_cell_model(CWcs(src_wcs).s, CWcs(tgt_wcs).s,
+                                                      int(cx), int(cy))
+    _check(s, "dfr_cell_model")
+    return {"coef_x": np.array(mx), "coef_y": np.array(my), "base": base, "bound": bound,
+            "certified": bool(cert)}
 
 
 def release():

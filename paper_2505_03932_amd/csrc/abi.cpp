@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "cell_model.hpp"
 #include "dfr.h"
 #include "launch.hpp"
 #include "plan.hpp"
@@ -22,10 +23,30 @@ dfr_status resolve_options(const dfr_options *opt, dfr_options &o) {
   if (!opt) return DFR_OK;
   if (opt->size != sizeof(dfr_options)) return DFR_E_ARG;
   o = *opt;
-  if (o.precision < DFR_PREC_F32 || o.precision > DFR_PREC_TRIG_F64) return DFR_E_UNSUPPORTED;
+  if (o.precision < DFR_PREC_F32 || o.precision > DFR_PREC_F32_ANCHOR) return DFR_E_UNSUPPORTED;
   if (!std::isfinite(o.cubic_a)) return DFR_E_ARG;
   if (o.tile < 0 || o.tile > kTileCount) return DFR_E_ARG;
   return DFR_OK;
+}
+
+bool is_f32(const dfr_options &o) {
+  return o.precision == DFR_PREC_F32 || o.precision == DFR_PREC_F32_ANCHOR;
+}
+
+// FP32 forward of one frame with tile `tile`: the per-cell position models
+// first where the map allows them (default precision, target without SIP;
+// the table lives in the stream's workspace, so the caller holds
+// workspace_mutex() from here until every launch reading it is queued).
+dfr_status models_for(FramePlan &P, int32_t out_h, int32_t out_w, const dfr_options &o,
+                      hipStream_t st) {
+  P.models = nullptr;
+  if (o.precision != DFR_PREC_F32 || P.t_order > 0) return DFR_OK;
+  const int ncx = (out_w + kCell - 1) / kCell, ncy = (out_h + kCell - 1) / kCell;
+  void *buf = workspace_buffer(workspace(st), (size_t)ncx * ncy * sizeof(CellModel));
+  if (!buf) return DFR_E_NOMEM;
+  CellModel *table = static_cast<CellModel *>(buf);
+  P.models = table;
+  return launch_cell_models(P, ncx, ncy, table, st) == hipSuccess ? DFR_OK : DFR_E_DEVICE;
 }
 
 bool interp_ok(int interp) {
@@ -86,7 +107,7 @@ dfr_status prepare_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_
   if ((s = check_wcs(tgt_wcs, false)) != DFR_OK) return s;
   dfr_options o;
   if ((s = resolve_options(opt, o)) != DFR_OK) return s;
-  if (o.precision != DFR_PREC_F32) return DFR_E_UNSUPPORTED;
+  if (!is_f32(o)) return DFR_E_UNSUPPORTED;
   if (o.debug_positions) return DFR_E_ARG;
   if ((int64_t)n * (((int64_t)out_h * out_w + 1023) / 1024) > 0x7fffffffLL) return DFR_E_SHAPE;
   for (int i = 0; i < n; ++i) {
@@ -186,11 +207,13 @@ dfr_status dfr_reproject(const float *src, int32_t src_h, int32_t src_w, int64_t
   build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, out, footprint, P);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipError_t e;
-  if (o.precision == DFR_PREC_F32) {
+  if (is_f32(o)) {
     TileGeom G;
     TileShape ts;
     int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false);
     make_geom(P, out_h, out_w, (int)interp, tile, o, G, ts);
+    std::lock_guard<std::mutex> lk(workspace_mutex());
+    if ((s = models_for(P, out_h, out_w, o, st)) != DFR_OK) return s;
     e = launch_forward_f32(P, G, (int)interp, ts.np, st);
   } else {
     TrigPlan T;
@@ -213,8 +236,10 @@ dfr_status dfr_reproject_batch(int32_t n, const dfr_frame *frames, const dfr_wcs
   dfr_status s = prepare_batch(n, frames, tgt_wcs, out_h, out_w, (int)interp, outs, footprints,
                                opt, plans, G, tile, np, max_sord);
   if (s != DFR_OK || plans.empty() || G.n_tiles == 0) return s;
-  return run_batch(plans, G, (int)interp, np, max_sord, reinterpret_cast<hipStream_t>(stream),
-                   true);
+  dfr_options o;
+  resolve_options(opt, o);
+  return run_batch(plans, G, (int)interp, np, max_sord, o.precision == DFR_PREC_F32,
+                   reinterpret_cast<hipStream_t>(stream), true);
 }
 
 dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w,
@@ -227,7 +252,7 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
   if (s != DFR_OK) return s;
   dfr_options o;
   if ((s = resolve_options(opt, o)) != DFR_OK) return s;
-  if (o.precision != DFR_PREC_F32) return DFR_E_UNSUPPORTED;
+  if (!is_f32(o)) return DFR_E_UNSUPPORTED;
   if (std::max(src_wcs->ap_order, src_wcs->bp_order) > 5) return DFR_E_UNSUPPORTED;
   if ((int64_t)out_h * out_w > 0 && !grad_out) return DFR_E_NULL;
   if (src_h == 0 || src_w == 0) src = nullptr;
@@ -290,7 +315,7 @@ dfr_status dfr_autotune(const float *src, int32_t src_h, int32_t src_w, int64_t 
   if (s != DFR_OK) return s;
   dfr_options o;
   if ((s = resolve_options(opt, o)) != DFR_OK) return s;
-  if (o.precision != DFR_PREC_F32) return DFR_E_UNSUPPORTED;
+  if (!is_f32(o)) return DFR_E_UNSUPPORTED;
   if (out_h == 0 || out_w == 0 || src_h == 0 || src_w == 0) {
     if (tile) *tile = kDefaultTile;
     return DFR_OK;
@@ -300,6 +325,9 @@ dfr_status dfr_autotune(const float *src, int32_t src_h, int32_t src_w, int64_t 
   FramePlan P;
   build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, out, footprint, P);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // the models do not depend on the tile: computed once, the tile kernels timed
+  std::lock_guard<std::mutex> lk(workspace_mutex());
+  if ((s = models_for(P, out_h, out_w, o, st)) != DFR_OK) return s;
   auto run = [&](int t) -> bool {
     TileGeom G;
     TileShape ts;
@@ -335,7 +363,8 @@ dfr_status dfr_autotune_batch(int32_t n, const dfr_frame *frames, const dfr_wcs 
     TileGeom Gt;
     int npt = 0;
     batch_geom(plans, out_h, out_w, (int)interp, t, o, Gt, npt);
-    return run_batch(plans, Gt, (int)interp, npt, max_sord, st, false) == DFR_OK;
+    return run_batch(plans, Gt, (int)interp, npt, max_sord, o.precision == DFR_PREC_F32, st,
+                     false) == DFR_OK;
   };
   int best = 0;
   s = time_candidates(run, st, best);
@@ -373,6 +402,32 @@ void dfr_cd_from_pc_cdelt(const double pc[4], const double cdelt[2], double cd[4
   cd[1] = cdelt[0] * pc[1];
   cd[2] = cdelt[1] * pc[2];
   cd[3] = cdelt[1] * pc[3];
+}
+
+dfr_status dfr_cell_model(const dfr_wcs *src_wcs, const dfr_wcs *tgt_wcs, int32_t cx, int32_t cy,
+                          double coef_x[10], double coef_y[10], int32_t base[2], double *bound,
+                          int32_t *certified) {
+  if (!src_wcs || !tgt_wcs) return DFR_E_NULL;
+  if (cx < 0 || cy < 0 || cx >= (1 << 25) || cy >= (1 << 25)) return DFR_E_ARG;
+  dfr_status s;
+  if ((s = check_wcs(src_wcs, true)) != DFR_OK) return s;
+  if ((s = check_wcs(tgt_wcs, false)) != DFR_OK) return s;
+  FramePlan P;
+  build_plan(nullptr, 0, 0, 0, *src_wcs, *tgt_wcs, (cy + 1) * kCell, (cx + 1) * kCell, nullptr,
+             nullptr, P);
+  CellModel M;
+  cell_model<-1>(P, cx, cy, M);
+  for (int k = 0; k < 10; ++k) {
+    if (coef_x) coef_x[k] = M.mx[k];
+    if (coef_y) coef_y[k] = M.my[k];
+  }
+  if (base) {
+    base[0] = M.bx;
+    base[1] = M.by;
+  }
+  if (bound) *bound = M.err;
+  if (certified) *certified = M.certified;
+  return DFR_OK;
 }
 
 dfr_status dfr_check_wcs(const dfr_wcs *wcs, int32_t as_source) {

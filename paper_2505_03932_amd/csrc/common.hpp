@@ -43,6 +43,8 @@ __host__ __device__ constexpr int tri_n(int n, int p, int q) {
   return p * (n + 1) - p * (p - 1) / 2 + q;
 }
 
+struct CellModel;
+
 // Everything a kernel needs about one source frame and the target grid.
 // Built on the host in FP64 (plan.cpp); passed by value (single image) or
 // through a device table (batch).
@@ -62,6 +64,7 @@ struct FramePlan {
   int32_t s_order;          // source AP/BP order (0 = none)
   int32_t series;           // 1: |k.d| < 1e-3 over the frame, 1/(1+e) = 1 - e + e^2
   int32_t pad_;
+  const CellModel *models;  // device table of per-cell position models, or null
   double tA[kMaxCoef], tB[kMaxCoef];   // FP64 coefficients, packed by tri9
   double sA[kMaxCoef], sB[kMaxCoef];
   float ftA[kMaxCoef], ftB[kMaxCoef];  // FP32, scaled: c * S^(p+q)

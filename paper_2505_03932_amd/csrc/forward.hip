@@ -25,6 +25,69 @@ hipError_t launch_forward_f32(const FramePlan &P, const TileGeom &G, int interp,
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ cell models
+
+// One lane per 32x32 cell of the output grid: the certified cubic model of
+// the cell's position map (cell_model.hpp), written to the model table.
+template <int SORD>
+__global__ __launch_bounds__(64) void cell_models_kernel(FramePlan P, int ncx, int n,
+                                                        CellModel *__restrict__ out) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
+  const int cy = i / ncx, cx = i - cy * ncx;
+  CellModel M;
+  cell_model<SORD>(P, cx, cy, M);
+  out[i] = M;
+}
+
+// The same for every frame of a batch: lane i models cell i % ncells of
+// frame i / ncells into out[i] (the frame's table starts at frame * ncells).
+template <int SORD>
+__global__ __launch_bounds__(64) void cell_models_batch_kernel(const FramePlan *__restrict__ plans,
+                                                              int ncx, int ncells, int64_t total,
+                                                              CellModel *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (i >= total) return;
+  const int frame = (int)(i / ncells), c = (int)(i - (int64_t)frame * ncells);
+  const int cy = c / ncx, cx = c - cy * ncx;
+  // the frame table is read-only here: scalar loads through the constant
+  // address space
+  using ConstPlan = const __attribute__((address_space(4))) FramePlan;
+  ConstPlan *cp = (ConstPlan *)(plans + frame);
+  CellModel M;
+  cell_model<SORD>(*(const FramePlan *)cp, cx, cy, M);
+  out[i] = M;
+}
+
+const void *cell_models_batch_ptr(int sord) {
+  switch (sord) {
+    case 0: return reinterpret_cast<const void *>(cell_models_batch_kernel<0>);
+    case 1: return reinterpret_cast<const void *>(cell_models_batch_kernel<1>);
+    case 2: return reinterpret_cast<const void *>(cell_models_batch_kernel<2>);
+    case 3: return reinterpret_cast<const void *>(cell_models_batch_kernel<3>);
+    case 4: return reinterpret_cast<const void *>(cell_models_batch_kernel<4>);
+    case 5: return reinterpret_cast<const void *>(cell_models_batch_kernel<5>);
+    default: return reinterpret_cast<const void *>(cell_models_batch_kernel<-1>);
+  }
+}
+
+hipError_t launch_cell_models(const FramePlan &P, int ncx, int ncy, CellModel *out,
+                              hipStream_t stream) {
+  const int n = ncx * ncy;
+  if (n <= 0) return hipSuccess;
+  const dim3 grid((n + 63) / 64), block(64);
+  switch (P.s_order) {
+    case 0: hipLaunchKernelGGL(cell_models_kernel<0>, grid, block, 0, stream, P, ncx, n, out); break;
+    case 1: hipLaunchKernelGGL(cell_models_kernel<1>, grid, block, 0, stream, P, ncx, n, out); break;
+    case 2: hipLaunchKernelGGL(cell_models_kernel<2>, grid, block, 0, stream, P, ncx, n, out); break;
+    case 3: hipLaunchKernelGGL(cell_models_kernel<3>, grid, block, 0, stream, P, ncx, n, out); break;
+    case 4: hipLaunchKernelGGL(cell_models_kernel<4>, grid, block, 0, stream, P, ncx, n, out); break;
+    case 5: hipLaunchKernelGGL(cell_models_kernel<5>, grid, block, 0, stream, P, ncx, n, out); break;
+    default: hipLaunchKernelGGL(cell_models_kernel<-1>, grid, block, 0, stream, P, ncx, n, out); break;
+  }
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------ FP64 comparison forms
 
 // FP64 interpolation at (xs, ys) with zero padding; same rules as the FP32

@@ -15,6 +15,7 @@
 //     comment above forward_tile).
 #pragma once
 
+#include "cell_model.hpp"
 #include "common.hpp"
 
 namespace dfr {
@@ -86,9 +87,6 @@ struct TileShared {
   Anchor anchor[kMaxAnchors];
   int box[4];     // imin, imax, jmin, jmax of the source box
   int touch;      // any anchor cell can reach the source
-  int item;       // batch: work item handed to this work-group
-  int cells_ok;   // forward: every anchor cell has valid positions throughout
-  int box_ok;     // forward: the anchors' linear models give a usable box
 };
 
 template <int INTERP>
@@ -302,23 +300,11 @@ __device__ __forceinline__ bool nearest_exact(const FramePlan &P, int x, int y, 
   return ok;
 }
 
-// -------------------------------------------------------------- forward --
+// ------------------------------------------------ shared by the forward --
 //
-// The forward tile runs a different schedule from the one above, built so
-// that the source staging overlaps the position arithmetic:
-//   1. wave 0: the FP64 anchors of the tile's cells; wave 1, at the same
-//      time: FP64 source positions at 9 points of the tile (corners, edge
-//      midpoints, centre) giving the tile's source box, grown by the tap
-//      support and 2 px;
-//   2. the box is staged into LDS with asynchronous global->LDS DMA loads
-//      (gfx950 global_load_lds_dword), row by row;
-//   3. meanwhile every pixel's FP32 position is computed;
-//   4. wait for the DMA, then gather.  A tile whose box lies inside the
-//      source, whose cells all have valid positions and which lies inside the
-//      output takes an unmasked path (footprint exactly 1); every pixel is
-//      still checked against the box and a wave with any pixel outside it
-//      takes the general (masked, global-fallback) path, so the box is only
-//      a performance hint.
+// Interpolation, store and position helpers of the forward kernels
+// (forward_cells.hpp): the interior formulas below are the ones every path
+// uses, so results agree bit for bit wherever all taps are inside.
 
 // Values of one pixel's in-image taps combined the same way on every path
 // (so all paths agree bit for bit where all taps are inside the source).
@@ -438,277 +424,48 @@ __device__ __forceinline__ void tap_origin(float r, int base, int &i0, float &t)
   }
 }
 
-// Stage rows [bj0, bj0+bh) x columns [bi0, bi0+bw) of the source into LDS
-// (row stride bw) with asynchronous DMA: one wave per row, 64 columns per
-// instruction, lanes past the row end masked off.
-__device__ __forceinline__ void dma_box(const FramePlan &P, int bi0, int bj0, int bw, int bh,
-                                        float *__restrict__ lds) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const float *__restrict__ s0 = P.src + (int64_t)bj0 * P.pitch + bi0;
-#pragma unroll 1
-  for (int r = wave; r < bh; r += kThreads / 64) {
-    const float *sr = s0 + (int64_t)r * P.pitch;
-#pragma unroll 1
-    for (int c0 = 0; c0 < bw; c0 += 64) {
-      if (c0 + lane < bw)
-        __builtin_amdgcn_global_load_lds(sr + c0 + lane, lds + r * bw + c0, 4, 0, 0);
-    }
-  }
+// A row of a cell model: the cubic in a at fixed b, four coefficients per
+// axis (Horner in b, once per row).
+struct ModelRow {
+  float x0, x1, x2, x3, y0, y1, y2, y3;
+};
+
+__device__ __forceinline__ void model_row(const CellModel &M, float b, ModelRow &R) {
+  R.x0 = fmaf(fmaf(fmaf(M.mx[3], b, M.mx[2]), b, M.mx[1]), b, M.mx[0]);
+  R.x1 = fmaf(fmaf(M.mx[6], b, M.mx[5]), b, M.mx[4]);
+  R.x2 = fmaf(M.mx[8], b, M.mx[7]);
+  R.x3 = M.mx[9];
+  R.y0 = fmaf(fmaf(fmaf(M.my[3], b, M.my[2]), b, M.my[1]), b, M.my[0]);
+  R.y1 = fmaf(fmaf(M.my[6], b, M.my[5]), b, M.my[4]);
+  R.y2 = fmaf(M.my[8], b, M.my[7]);
+  R.y3 = M.my[9];
 }
 
-// The target SIP is compiled only into the run-time-order variant (the
-// launcher uses it whenever the target WCS has A/B).
-template <int INTERP, int SORD, int NP>
-__device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom &G, int tile,
-                                             float *__restrict__ lds, TileShared &sh) {
-  constexpr bool TSIP = SORD == kRtOrder;
-  const int tid = threadIdx.x, wave = tid >> 6;
-  const int lg = G.txt_log2;
-  const int TW = kRun << lg, RP = kThreads >> lg, TH = RP * NP;
-  const int trow = tile / G.tiles_x;
-  const int x0 = (tile - trow * G.tiles_x) * TW, y0 = trow * TH;
-  const int cx0 = x0 / kCell, ncx = TW / kCell, cy0 = y0 / kCell;
-  const int nA = ncx * (TH >= kCell ? TH / kCell : 1);
-  const int ty = tid >> lg, xr = x0 + (tid & ((1 << lg) - 1)) * kRun;
-  const int W = P.src_w, Hs = P.src_h;
+// Source position (relative to the model's base) of the pixel at column
+// offset a from the cell centre.
+__device__ __forceinline__ void model_at(const ModelRow &R, float a, float &px, float &py) {
+  px = fmaf(fmaf(fmaf(R.x3, a, R.x2), a, R.x1), a, R.x0);
+  py = fmaf(fmaf(fmaf(R.y3, a, R.y2), a, R.y1), a, R.y0);
+}
 
-  // ---- 1. anchors (FP64) and, from their linear models, the source box
-  if (wave == 0) {
-    constexpr int lo = TapSupport<INTERP>::lo + 2, hi = TapSupport<INTERP>::hi + 2;
-    int t = 0, okc = 1;
-    int imn = 0x3fffffff, imx = -0x3fffffff, jmn = 0x3fffffff, jmx = -0x3fffffff;
-    if (tid < nA) {
-      const int cy = cy0 + tid / ncx, cx = cx0 + tid % ncx;
-      const int xa = cx * kCell, ya = cy * kCell;
-      Anchor &A = sh.anchor[tid];
-      compute_anchor<SORD, TSIP>(P, xa, ya, TapSupport<INTERP>::hi, A);
-      t = A.touch;
-      okc = A.ok;
-      // the part of the cell inside the tile and the output, as offsets
-      const float ux = (float)(min(xa + kCell, min(x0 + TW, G.out_w)) - 1 - xa);
-      const float vy0 = (float)(max(ya, y0) - ya);
-      const float vy1 = (float)(min(ya + kCell, min(y0 + TH, G.out_h)) - 1 - ya);
-      // extremes of the linear model over that rectangle, grown by the
-      // rigorous bound on the model's error, relative to (bx, by)
-      const float mx = A.ex, my = A.ey;
-      const float x_a = A.sx0 + fminf(0.0f, A.jx[0] * ux) + fminf(A.jx[1] * vy0, A.jx[1] * vy1) - mx;
-      const float x_b = A.sx0 + fmaxf(0.0f, A.jx[0] * ux) + fmaxf(A.jx[1] * vy0, A.jx[1] * vy1) + mx;
-      const float y_a = A.sy0 + fminf(0.0f, A.jy[0] * ux) + fminf(A.jy[1] * vy0, A.jy[1] * vy1) - my;
-      const float y_b = A.sy0 + fmaxf(0.0f, A.jy[0] * ux) + fmaxf(A.jy[1] * vy0, A.jy[1] * vy1) + my;
-      if (okc && fabsf(x_a) < 1.0e7f && fabsf(x_b) < 1.0e7f && fabsf(y_a) < 1.0e7f &&
-          fabsf(y_b) < 1.0e7f) {
-        imn = A.bx + (int)floorf(x_a) - lo;
-        imx = A.bx + (int)floorf(x_b) + hi;
-        jmn = A.by + (int)floorf(y_a) - lo;
-        jmx = A.by + (int)floorf(y_b) + hi;
-      } else {
-        okc = 0;
-      }
-    }
-#pragma unroll
-    for (int m = kMaxAnchors / 2; m >= 1; m >>= 1) {
-      imn = min(imn, __shfl_xor(imn, m, 64));
-      imx = max(imx, __shfl_xor(imx, m, 64));
-      jmn = min(jmn, __shfl_xor(jmn, m, 64));
-      jmx = max(jmx, __shfl_xor(jmx, m, 64));
-    }
-    const unsigned long long any = __ballot(t != 0), bad = __ballot(okc == 0);
-    if (tid == 0) {
-      sh.touch = any != 0ull;
-      sh.cells_ok = bad == 0ull;
-      sh.box_ok = bad == 0ull;
-      sh.box[0] = imn;
-      sh.box[1] = imx;
-      sh.box[2] = jmn;
-      sh.box[3] = jmx;
-    }
-  }
-  __syncthreads();
-
-  const bool vec = vector_stores_ok(P, G);
-  const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
-  if (!sh.touch && G.allow_skip) {
-    float zo[kRun], zf[kRun];
-#pragma unroll
-    for (int e = 0; e < kRun; ++e) {
-      zo[e] = miss;
-      zf[e] = 0.0f;
-    }
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      int y = y0 + ty + k * RP;
-      if (y >= G.out_h || xr >= G.out_w) continue;
-      int64_t off = (int64_t)y * G.out_w + xr;
-      store_run(P.out, off, xr, G.out_w, vec, zo);
-      if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, zf);
-    }
-    return;
-  }
-
-  // ---- 2. stage the box (asynchronous)
-  const int bu0 = sh.box[0], bu1 = sh.box[1], bu2 = sh.box[2], bu3 = sh.box[3];
-  const int bi0 = max(bu0, 0), bi1 = min(bu1, W - 1), bj0 = max(bu2, 0), bj1 = min(bu3, Hs - 1);
-  const bool box_ok = sh.box_ok && bi0 <= bi1 && bj0 <= bj1;
-  const int bw = box_ok ? bi1 - bi0 + 1 : 0, bh = box_ok ? bj1 - bj0 + 1 : 0;
-  const bool use_lds = box_ok && (int64_t)bw * bh <= (int64_t)G.lds_cap;
-  const bool interior = use_lds && sh.cells_ok && P.t_order == 0 && bu0 == bi0 && bu1 == bi1 &&
-                        bu2 == bj0 && bu3 == bj1 && x0 + TW <= G.out_w && y0 + TH <= G.out_h;
-  if (use_lds) dma_box(P, bi0, bj0, bw, bh, lds);
-
-  // ---- 3. positions (FP32 offsets from the anchors)
-  const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
-  float rx[NP][kRun], ry[NP][kRun];
-  int abx[NP], aby[NP];
-  unsigned valid = 0u;
-  if (interior && !G.debug) {
-    // every cell is valid throughout and the tile lies inside the output
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const int y = y0 + ty + k * RP;
-      const Anchor &A = sh.anchor[((y >> kCellLog2) - cy0) * ncx + ((xr >> kCellLog2) - cx0)];
-      abx[k] = A.bx - bi0;
-      aby[k] = A.by - bj0;
-      const float dy = (float)(y & (kCell - 1));
-#pragma unroll
-      for (int e = 0; e < kRun; ++e) {
-        float px, py;
-        pixel_position<SORD, TSIP>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy, px, py);
-        if constexpr (INTERP == DFR_NEAREST) {
-          // a rounding decision within reach of the FP32 error: decide in FP64
-          float tx_ = px - floorf(px), ty_ = py - floorf(py);
-          if (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f) {
-            double xs, ys;
-            nearest_exact<SORD, TSIP>(P, xr + e, y, A.bx, A.by, px, py, xs, ys);
-          }
-        }
-        rx[k][e] = px;
-        ry[k][e] = py;
-      }
-    }
-    valid = ~0u;
+// Debug output: the FP64 source position of output pixel (x, y) as the
+// kernel used it (NaN where invalid); only for pixels inside the output.
+__device__ __forceinline__ void debug_position(const TileGeom &G, int x, int y, bool ok,
+                                               bool exact, double dbx, double dby, int bx, int by,
+                                               float px, float py) {
+  if (y >= G.out_h || x >= G.out_w) return;
+  double2 d;
+  if (!ok) {
+    d.x = __builtin_nan("");
+    d.y = d.x;
+  } else if (exact) {
+    d.x = dbx;
+    d.y = dby;
   } else {
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const int y = y0 + ty + k * RP;
-      const Anchor &A = sh.anchor[((y >> kCellLog2) - cy0) * ncx + ((xr >> kCellLog2) - cx0)];
-      abx[k] = A.bx - bi0;
-      aby[k] = A.by - bj0;
-      const float dy = (float)(y & (kCell - 1));
-#pragma unroll
-      for (int e = 0; e < kRun; ++e) {
-        const int x = xr + e;
-        float px, py;
-        bool ok = pixel_position<SORD, TSIP>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy,
-                                       px, py);
-        ok = ok && (y < G.out_h) && (x < G.out_w);
-        double dbx = 0.0, dby = 0.0;
-        bool exact = false;
-        if constexpr (INTERP == DFR_NEAREST) {
-          // a rounding decision within reach of the FP32 error: decide in FP64
-          float tx_ = px - floorf(px), ty_ = py - floorf(py);
-          if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
-            ok = nearest_exact<SORD, TSIP>(P, x, y, A.bx, A.by, px, py, dbx, dby);
-            exact = ok;
-          }
-        }
-        rx[k][e] = px;
-        ry[k][e] = py;
-        if (G.debug && y < G.out_h && x < G.out_w) {
-          double2 d;
-          if (!ok) {
-            d.x = __builtin_nan("");
-            d.y = d.x;
-          } else if (exact) {
-            d.x = dbx;
-            d.y = dby;
-          } else {
-            d.x = (double)A.bx + (double)px;
-            d.y = (double)A.by + (double)py;
-          }
-          reinterpret_cast<double2 *>(G.debug)[(int64_t)y * G.out_w + x] = d;
-        }
-        if (ok) valid |= 1u << (k * kRun + e);
-      }
-    }
+    d.x = (double)bx + (double)px;
+    d.y = (double)by + (double)py;
   }
-
-  // ---- 4. gather
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  constexpr int SPAN = TapSupport<INTERP>::lo + TapSupport<INTERP>::hi;
-  // Interior tiles need no per-pixel check: the box holds every tap by the
-  // rigorous margin of the anchors' linear models.
-  const bool fast = interior && valid == ~0u;
-  const float a = G.cubic_a;
-  if (fast) {
-    // box-relative tap coordinates: unmasked LDS reads from one base address
-    // per pixel, footprint exactly 1
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const int y = y0 + ty + k * RP;
-      float o[kRun], f[kRun];
-#pragma unroll
-      for (int e = 0; e < kRun; ++e) {
-        int i0, j0;
-        float t_, s_;
-        tap_origin<INTERP>(rx[k][e], abx[k], i0, t_);
-        tap_origin<INTERP>(ry[k][e], aby[k], j0, s_);
-        // i0, j0 >= 0 inside the box: one 24-bit multiply-add per pixel
-        const float *__restrict__ b = lds + __umul24(j0, bw) + i0;
-        auto fl = [&](int i, int j) -> float { return b[j * bw + i]; };
-        if constexpr (INTERP == DFR_NEAREST) {
-          o[e] = b[0];
-        } else if constexpr (INTERP == DFR_BILINEAR) {
-          o[e] = Taps<DFR_BILINEAR>::interior(0, 0, t_, s_, fl);
-        } else {
-          float wx[4], wy[4];
-          keys_weights(t_, a, wx);
-          keys_weights(s_, a, wy);
-          o[e] = Taps<DFR_BICUBIC>::interior(0, 0, wx, wy, fl);
-        }
-        f[e] = 1.0f;
-      }
-      const int64_t off = (int64_t)y * G.out_w + xr;
-      store_run(P.out, off, xr, G.out_w, vec, o);
-      if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, f);
-    }
-    return;
-  }
-  // general path: source coordinates, zero padding, footprint normalisation;
-  // taps come from LDS when the pixel's in-image taps are inside the box
-  auto fl = [&](int i, int j) -> float { return lds[__umul24(j - bj0, bw) + (i - bi0)]; };
-  auto fg = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
-#pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    const int y = y0 + ty + k * RP;
-    if (y >= G.out_h || xr >= G.out_w) continue;
-    float o[kRun], f[kRun];
-#pragma unroll
-    for (int e = 0; e < kRun; ++e) {
-      o[e] = miss;
-      f[e] = 0.0f;
-      if (valid & (1u << (k * kRun + e))) {
-        int i0, j0;
-        float t_, s_;
-        tap_origin<INTERP>(rx[k][e], abx[k] + bi0, i0, t_);
-        tap_origin<INTERP>(ry[k][e], aby[k] + bj0, j0, s_);
-        const bool in_lds = use_lds && max(i0, 0) >= bi0 && min(i0 + SPAN, W - 1) <= bi1 &&
-                            max(j0, 0) >= bj0 && min(j0 + SPAN, Hs - 1) <= bj1;
-        float ov, fv;
-        if (in_lds)
-          interp_general<INTERP>(i0, j0, t_, s_, W, Hs, a, fl, ov, fv);
-        else
-          interp_general<INTERP>(i0, j0, t_, s_, W, Hs, a, fg, ov, fv);
-        if (fv > 0.0f) {
-          o[e] = ov;
-          f[e] = fv;
-        }
-      }
-    }
-    const int64_t off = (int64_t)y * G.out_w + xr;
-    store_run(P.out, off, xr, G.out_w, vec, o);
-    if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, f);
-  }
+  reinterpret_cast<double2 *>(G.debug)[(int64_t)y * G.out_w + x] = d;
 }
 
 }  // namespace dfr

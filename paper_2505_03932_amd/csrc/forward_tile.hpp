@@ -1,0 +1,357 @@
+// Forward reprojection of one output tile per work-group (section 3.1 for
+// every pixel: the two stages of section 3.2 give the source position, then
+// interpolation and footprint normalisation).
+//
+// A tile is (kRun << txt_log2) x ((kThreads >> txt_log2) * NP) output
+// pixels.  Thread (tx, ty) owns NP runs of kRun consecutive pixels in rows
+// ty, ty + RP, ..., so every wave store covers contiguous row segments.
+//   1. wave 0: per cell of the tile (32x32 output pixels) its certified
+//      position model (cell_model.hpp) from the model table, else its FP64
+//      anchor; from them a rigorous source box, grown by the tap support;
+//   2. the box is staged into LDS with asynchronous global->LDS DMA loads
+//      (gfx950 global_load_lds_dword), row by row, by all waves;
+//   3. meanwhile every pixel's FP32 source position is computed;
+//   4. wait for the DMA, then gather.  A tile whose box lies inside the
+//      source, whose cells all have valid positions and which lies inside the
+//      output is gathered without per-pixel checks (footprint exactly 1);
+//      others take the general path (zero padding, footprint normalisation,
+//      global fetches for taps outside the box).
+// Positions depend only on the pixel's cell (its model or anchor), never on
+// the tile shape, so every tile shape and the batch give identical results.
+#pragma once
+
+#include "forward_body.hpp"
+
+namespace dfr {
+
+// LDS of a forward work-group besides the staged source box.
+struct FwdShared {
+  union CellSlot {
+    Anchor anchor;
+    CellModel model;
+  } cell[kMaxAnchors];
+  int kind[kMaxAnchors];  // 1: cell[i].model, 0: cell[i].anchor
+  int box[4];             // imin, imax, jmin, jmax of the source box
+  int touch;              // some cell can reach the source
+  int cells_ok;           // every cell has valid positions throughout
+  int box_ok;             // the box is finite
+  int all_model;          // every cell has a model
+  int item;               // batch: work item handed to this work-group
+};
+
+// Stage rows [bj0, bj0+bh) x columns [bi0, bi0+bw) of the source into LDS
+// (row stride bw) with asynchronous DMA: one wave per row, 64 columns per
+// instruction, lanes past the row end masked off.
+__device__ __forceinline__ void dma_box(const FramePlan &P, int bi0, int bj0, int bw, int bh,
+                                        float *__restrict__ lds) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const float *__restrict__ s0 = P.src + (int64_t)bj0 * P.pitch + bi0;
+#pragma unroll 1
+  for (int r = wave; r < bh; r += kThreads / 64) {
+    const float *sr = s0 + (int64_t)r * P.pitch;
+#pragma unroll 1
+    for (int c0 = 0; c0 < bw; c0 += 64) {
+      if (c0 + lane < bw)
+        __builtin_amdgcn_global_load_lds(sr + c0 + lane, lds + r * bw + c0, 4, 0, 0);
+    }
+  }
+}
+
+// The target SIP is compiled only into the run-time-order variant (the
+// launcher uses it whenever the target WCS has A/B).
+template <int INTERP, int SORD, int NP>
+__device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom &G, int tile,
+                                             float *__restrict__ lds, FwdShared &sh) {
+  constexpr bool TSIP = SORD == kRtOrder;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int lg = G.txt_log2;
+  const int TW = kRun << lg, RP = kThreads >> lg, TH = RP * NP;
+  const int trow = tile / G.tiles_x;
+  const int x0 = (tile - trow * G.tiles_x) * TW, y0 = trow * TH;
+  const int cx0 = x0 / kCell, ncx = TW / kCell, cy0 = y0 / kCell;
+  const int nA = ncx * (TH >= kCell ? TH / kCell : 1);
+  const int ty = tid >> lg, xr = x0 + (tid & ((1 << lg) - 1)) * kRun;
+  const int W = P.src_w, Hs = P.src_h;
+
+  // ---- 1. per cell: its certified model from the model table, else its
+  // FP64 anchor; from them the source box
+  if (wave == 0) {
+    int t = 0, okc = 1, kind = 0;
+    int imn = 0x3fffffff, imx = -0x3fffffff, jmn = 0x3fffffff, jmx = -0x3fffffff;
+    if (tid < nA) {
+      const int cy = cy0 + tid / ncx, cx = cx0 + tid % ncx;
+      const int xa = cx * kCell, ya = cy * kCell;
+      if (P.models) {
+        const CellModel *Mg = P.models + (cy * ((G.out_w + kCell - 1) >> kCellLog2) + cx);
+        kind = Mg->certified;
+        if (kind) {
+          // the model covers every pixel of the cell: the box needs only the
+          // tap support (+1 px kept as a guard)
+          constexpr int lo = TapSupport<INTERP>::lo + 1, hi = TapSupport<INTERP>::hi + 1;
+#pragma unroll
+          for (int part = 0; part < (int)(sizeof(CellModel) / 16); ++part)
+            reinterpret_cast<uint4 *>(&sh.cell[tid].model)[part] =
+                reinterpret_cast<const uint4 *>(Mg)[part];
+          const CellModel &M = sh.cell[tid].model;
+          // the part of the cell inside the tile and the output, as offsets
+          // from the cell centre; extremes of the linear part there, grown
+          // by the bound on the rest
+          const float h = (float)kHalfCell;
+          const float a0 = (float)(max(xa, x0) - xa) - h;
+          const float a1 = (float)(min(xa + kCell, min(x0 + TW, G.out_w)) - 1 - xa) - h;
+          const float b0 = (float)(max(ya, y0) - ya) - h;
+          const float b1 = (float)(min(ya + kCell, min(y0 + TH, G.out_h)) - 1 - ya) - h;
+          const float xl = M.mx[0] + fminf(M.mx[4] * a0, M.mx[4] * a1) + fminf(M.mx[1] * b0, M.mx[1] * b1) - M.ex;
+          const float xh = M.mx[0] + fmaxf(M.mx[4] * a0, M.mx[4] * a1) + fmaxf(M.mx[1] * b0, M.mx[1] * b1) + M.ex;
+          const float yl = M.my[0] + fminf(M.my[4] * a0, M.my[4] * a1) + fminf(M.my[1] * b0, M.my[1] * b1) - M.ey;
+          const float yh = M.my[0] + fmaxf(M.my[4] * a0, M.my[4] * a1) + fmaxf(M.my[1] * b0, M.my[1] * b1) + M.ey;
+          imn = M.bx + (int)floorf(xl) - lo;
+          imx = M.bx + (int)floorf(xh) + hi;
+          jmn = M.by + (int)floorf(yl) - lo;
+          jmx = M.by + (int)floorf(yh) + hi;
+          t = (imx >= 0 && imn <= W - 1 && jmx >= 0 && jmn <= Hs - 1) ? 1 : 0;
+        }
+      }
+      if (!kind) {
+        constexpr int lo = TapSupport<INTERP>::lo + 2, hi = TapSupport<INTERP>::hi + 2;
+        Anchor &A = sh.cell[tid].anchor;
+        compute_anchor<SORD, TSIP>(P, xa, ya, TapSupport<INTERP>::hi, A);
+        t = A.touch;
+        okc = A.ok;
+        // the part of the cell inside the tile and the output, as offsets
+        const float ux = (float)(min(xa + kCell, min(x0 + TW, G.out_w)) - 1 - xa);
+        const float vy0 = (float)(max(ya, y0) - ya);
+        const float vy1 = (float)(min(ya + kCell, min(y0 + TH, G.out_h)) - 1 - ya);
+        // extremes of the linear model over that rectangle, grown by the
+        // rigorous bound on the model's error, relative to (bx, by)
+        const float mx = A.ex, my = A.ey;
+        const float x_a = A.sx0 + fminf(0.0f, A.jx[0] * ux) + fminf(A.jx[1] * vy0, A.jx[1] * vy1) - mx;
+        const float x_b = A.sx0 + fmaxf(0.0f, A.jx[0] * ux) + fmaxf(A.jx[1] * vy0, A.jx[1] * vy1) + mx;
+        const float y_a = A.sy0 + fminf(0.0f, A.jy[0] * ux) + fminf(A.jy[1] * vy0, A.jy[1] * vy1) - my;
+        const float y_b = A.sy0 + fmaxf(0.0f, A.jy[0] * ux) + fmaxf(A.jy[1] * vy0, A.jy[1] * vy1) + my;
+        if (okc && fabsf(x_a) < 1.0e7f && fabsf(x_b) < 1.0e7f && fabsf(y_a) < 1.0e7f &&
+            fabsf(y_b) < 1.0e7f) {
+          imn = A.bx + (int)floorf(x_a) - lo;
+          imx = A.bx + (int)floorf(x_b) + hi;
+          jmn = A.by + (int)floorf(y_a) - lo;
+          jmx = A.by + (int)floorf(y_b) + hi;
+        } else {
+          okc = 0;
+        }
+      }
+      sh.kind[tid] = kind;
+    }
+#pragma unroll
+    for (int m = kMaxAnchors / 2; m >= 1; m >>= 1) {
+      imn = min(imn, __shfl_xor(imn, m, 64));
+      imx = max(imx, __shfl_xor(imx, m, 64));
+      jmn = min(jmn, __shfl_xor(jmn, m, 64));
+      jmx = max(jmx, __shfl_xor(jmx, m, 64));
+    }
+    const unsigned long long any = __ballot(t != 0), bad = __ballot(okc == 0),
+                             anch = __ballot(tid < nA && kind == 0);
+    if (tid == 0) {
+      sh.touch = any != 0ull;
+      sh.cells_ok = bad == 0ull;
+      sh.box_ok = bad == 0ull;
+      sh.all_model = anch == 0ull;
+      sh.box[0] = imn;
+      sh.box[1] = imx;
+      sh.box[2] = jmn;
+      sh.box[3] = jmx;
+    }
+  }
+  __syncthreads();
+
+  const bool vec = vector_stores_ok(P, G);
+  const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
+  if (!sh.touch && G.allow_skip) {
+    // no pixel of the tile reaches the source
+    float zo[kRun], zf[kRun];
+#pragma unroll
+    for (int e = 0; e < kRun; ++e) {
+      zo[e] = miss;
+      zf[e] = 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int y = y0 + ty + k * RP;
+      if (y >= G.out_h || xr >= G.out_w) continue;
+      const int64_t off = (int64_t)y * G.out_w + xr;
+      store_run(P.out, off, xr, G.out_w, vec, zo);
+      if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, zf);
+    }
+    return;
+  }
+
+  // ---- 2. stage the box (asynchronous)
+  const int bu0 = sh.box[0], bu1 = sh.box[1], bu2 = sh.box[2], bu3 = sh.box[3];
+  const int bi0 = max(bu0, 0), bi1 = min(bu1, W - 1), bj0 = max(bu2, 0), bj1 = min(bu3, Hs - 1);
+  const bool box_ok = sh.box_ok && bi0 <= bi1 && bj0 <= bj1;
+  const int bw = box_ok ? bi1 - bi0 + 1 : 0, bh = box_ok ? bj1 - bj0 + 1 : 0;
+  const bool use_lds = box_ok && (int64_t)bw * bh <= (int64_t)G.lds_cap;
+  const bool interior = use_lds && sh.cells_ok && P.t_order == 0 && bu0 == bi0 && bu1 == bi1 &&
+                        bu2 == bj0 && bu3 == bj1 && x0 + TW <= G.out_w && y0 + TH <= G.out_h;
+  if (use_lds) dma_box(P, bi0, bj0, bw, bh, lds);
+
+  // ---- 3. positions: the cell's model, or FP32 offsets from its anchor
+  const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
+  const float hc = (float)kHalfCell;
+  float rx[NP][kRun], ry[NP][kRun];
+  int abx[NP], aby[NP];
+  unsigned valid = 0u;
+  if (sh.all_model && interior && !G.debug) {
+    // certified cubic models throughout, tile inside the output: every pixel
+    // is valid
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int y = y0 + ty + k * RP;
+      const CellModel &M = sh.cell[((y >> kCellLog2) - cy0) * ncx + ((xr >> kCellLog2) - cx0)].model;
+      abx[k] = M.bx - bi0;
+      aby[k] = M.by - bj0;
+      ModelRow R;
+      model_row(M, (float)(y & (kCell - 1)) - hc, R);
+      const float a0 = (float)(xr & (kCell - 1)) - hc;
+#pragma unroll
+      for (int e = 0; e < kRun; ++e) {
+        float px, py;
+        model_at(R, a0 + (float)e, px, py);
+        if constexpr (INTERP == DFR_NEAREST) {
+          // a rounding decision within reach of the FP32 error: decide in FP64
+          float tx_ = px - floorf(px), ty_ = py - floorf(py);
+          if (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f) {
+            double xs, ys;
+            nearest_exact<SORD, TSIP>(P, xr + e, y, M.bx, M.by, px, py, xs, ys);
+          }
+        }
+        rx[k][e] = px;
+        ry[k][e] = py;
+      }
+    }
+    valid = ~0u;
+  } else {
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int y = y0 + ty + k * RP;
+      const int ci = ((y >> kCellLog2) - cy0) * ncx + ((xr >> kCellLog2) - cx0);
+      const bool mk = sh.kind[ci] != 0;
+      const Anchor &A = sh.cell[ci].anchor;
+      const CellModel &M = sh.cell[ci].model;
+      const int bx = mk ? M.bx : A.bx, by = mk ? M.by : A.by;
+      abx[k] = bx - bi0;
+      aby[k] = by - bj0;
+      ModelRow R;
+      if (mk) model_row(M, (float)(y & (kCell - 1)) - hc, R);
+      const float dy = (float)(y & (kCell - 1));
+      const float a0 = (float)(xr & (kCell - 1)) - hc;
+#pragma unroll
+      for (int e = 0; e < kRun; ++e) {
+        const int x = xr + e;
+        float px, py;
+        bool ok;
+        if (mk) {
+          model_at(R, a0 + (float)e, px, py);
+          ok = true;
+        } else {
+          ok = pixel_position<SORD, TSIP>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy,
+                                          px, py);
+        }
+        ok = ok && (y < G.out_h) && (x < G.out_w);
+        double dbx = 0.0, dby = 0.0;
+        bool exact = false;
+        if constexpr (INTERP == DFR_NEAREST) {
+          // a rounding decision within reach of the FP32 error: decide in FP64
+          float tx_ = px - floorf(px), ty_ = py - floorf(py);
+          if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
+            ok = nearest_exact<SORD, TSIP>(P, x, y, bx, by, px, py, dbx, dby);
+            exact = ok;
+          }
+        }
+        rx[k][e] = px;
+        ry[k][e] = py;
+        if (G.debug) debug_position(G, x, y, ok, exact, dbx, dby, bx, by, px, py);
+        if (ok) valid |= 1u << (k * kRun + e);
+      }
+    }
+  }
+
+  // ---- 4. gather
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  constexpr int SPAN = TapSupport<INTERP>::lo + TapSupport<INTERP>::hi;
+  // Interior tiles need no per-pixel check: the box holds every tap by the
+  // rigorous margin of the anchors' linear models.
+  const bool fast = interior && valid == ~0u;
+  const float a = G.cubic_a;
+  if (fast) {
+    // box-relative tap coordinates: unmasked LDS reads from one base address
+    // per pixel, footprint exactly 1
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int y = y0 + ty + k * RP;
+      float o[kRun], f[kRun];
+#pragma unroll
+      for (int e = 0; e < kRun; ++e) {
+        int i0, j0;
+        float t_, s_;
+        tap_origin<INTERP>(rx[k][e], abx[k], i0, t_);
+        tap_origin<INTERP>(ry[k][e], aby[k], j0, s_);
+        // i0, j0 >= 0 inside the box: one 24-bit multiply-add per pixel
+        const float *__restrict__ b = lds + __umul24(j0, bw) + i0;
+        auto fl = [&](int i, int j) -> float { return b[j * bw + i]; };
+        if constexpr (INTERP == DFR_NEAREST) {
+          o[e] = b[0];
+        } else if constexpr (INTERP == DFR_BILINEAR) {
+          o[e] = Taps<DFR_BILINEAR>::interior(0, 0, t_, s_, fl);
+        } else {
+          float wx[4], wy[4];
+          keys_weights(t_, a, wx);
+          keys_weights(s_, a, wy);
+          o[e] = Taps<DFR_BICUBIC>::interior(0, 0, wx, wy, fl);
+        }
+        f[e] = 1.0f;
+      }
+      const int64_t off = (int64_t)y * G.out_w + xr;
+      store_run(P.out, off, xr, G.out_w, vec, o);
+      if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, f);
+    }
+    return;
+  }
+  // general path: source coordinates, zero padding, footprint normalisation;
+  // taps come from LDS when the pixel's in-image taps are inside the box
+  auto fl = [&](int i, int j) -> float { return lds[__umul24(j - bj0, bw) + (i - bi0)]; };
+  auto fg = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int y = y0 + ty + k * RP;
+    if (y >= G.out_h || xr >= G.out_w) continue;
+    float o[kRun], f[kRun];
+#pragma unroll
+    for (int e = 0; e < kRun; ++e) {
+      o[e] = miss;
+      f[e] = 0.0f;
+      if (valid & (1u << (k * kRun + e))) {
+        int i0, j0;
+        float t_, s_;
+        tap_origin<INTERP>(rx[k][e], abx[k] + bi0, i0, t_);
+        tap_origin<INTERP>(ry[k][e], aby[k] + bj0, j0, s_);
+        const bool in_lds = use_lds && max(i0, 0) >= bi0 && min(i0 + SPAN, W - 1) <= bi1 &&
+                            max(j0, 0) >= bj0 && min(j0 + SPAN, Hs - 1) <= bj1;
+        float ov, fv;
+        if (in_lds)
+          interp_general<INTERP>(i0, j0, t_, s_, W, Hs, a, fl, ov, fv);
+        else
+          interp_general<INTERP>(i0, j0, t_, s_, W, Hs, a, fg, ov, fv);
+        if (fv > 0.0f) {
+          o[e] = ov;
+          f[e] = fv;
+        }
+      }
+    }
+    const int64_t off = (int64_t)y * G.out_w + xr;
+    store_run(P.out, off, xr, G.out_w, vec, o);
+    if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, f);
+  }
+}
+
+}  // namespace dfr

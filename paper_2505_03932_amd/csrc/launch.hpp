@@ -39,6 +39,12 @@ struct TrigPlan {
 
 hipError_t launch_forward_f32(const FramePlan &P, const TileGeom &G, int interp, int np,
                               hipStream_t stream);
+// Per-cell position models of the output grid (ncx x ncy cells of 32x32).
+hipError_t launch_cell_models(const FramePlan &P, int ncx, int ncy, CellModel *out,
+                              hipStream_t stream);
+// Kernel (plans, ncx, ncells, total, out) modelling every cell of every
+// frame of a batch; sord as for the batch kernel.
+const void *cell_models_batch_ptr(int sord);
 hipError_t launch_forward_f64(const FramePlan &P, const TrigPlan &T, const TileGeom &G,
                               int interp, bool trig, hipStream_t stream);
 hipError_t launch_batch_f32(const FramePlan *plans_dev, int n_frames, int max_sord,

@@ -1,5 +1,6 @@
 // Host runtime: tile choice, the tuned-shape cache (optionally persisted as
 // JSON), launch geometry, per-device workspaces.
+#include "cell_model.hpp"
 #include "runtime.hpp"
 
 #include <algorithm>
@@ -220,16 +221,23 @@ void release_workspaces() {
 // ----------------------------------------------------------------- batch --
 
 dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int interp, int np,
-                     int max_sord, hipStream_t stream, bool graph) {
+                     int max_sord, bool models, hipStream_t stream, bool graph) {
   std::lock_guard<std::mutex> lk(g_ws_mutex);
   Workspace *w = workspace(stream);
   if (!w) return DFR_E_DEVICE;
   const int n = (int)plans.size();
   const size_t table = (size_t)n * sizeof(FramePlan);
-  char *dev = static_cast<char *>(workspace_buffer(w, 256 + table));
+  // counter | frame table | per-frame model tables (when used)
+  models = models && plans[0].t_order == 0;
+  const int ncx = (G.out_w + kCell - 1) / kCell, ncy = (G.out_h + kCell - 1) / kCell;
+  const int64_t ncells = (int64_t)ncx * ncy;
+  const size_t mofs = (256 + table + 255) & ~(size_t)255;
+  const size_t mbytes = models ? (size_t)n * ncells * sizeof(CellModel) : 0;
+  char *dev = static_cast<char *>(workspace_buffer(w, mofs + mbytes));
   if (!dev) return DFR_E_NOMEM;
   int *counter = reinterpret_cast<int *>(dev);
   FramePlan *plans_dev = reinterpret_cast<FramePlan *>(dev + 256);
+  CellModel *models_dev = models ? reinterpret_cast<CellModel *>(dev + mofs) : nullptr;
   // the previous batch on this stream must have copied the staged table
   if (w->staged_pending) {
     if (hipEventSynchronize(w->staged) != hipSuccess) return DFR_E_DEVICE;
@@ -245,6 +253,7 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
     w->host_cap = n;
   }
   std::memcpy(w->host_plans, plans.data(), table);
+  for (int i = 0; i < n; ++i) w->host_plans[i].models = models ? models_dev + i * ncells : nullptr;
   int dev_id = 0, cus = 0;
   if (hipGetDevice(&dev_id) != hipSuccess) return DFR_E_DEVICE;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess ||
@@ -252,9 +261,17 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
     cus = 1;
   const int lds_bytes = G.lds_cap * (int)sizeof(float);
   const int grid = batch_blocks_per_cu(interp, np, max_sord, lds_bytes) * cus;
+  const int64_t mtotal = (int64_t)n * ncells;
+  const dim3 mgrid((unsigned)((mtotal + 63) / 64));
+  int ncx_i = ncx, ncells_i = (int)ncells;
+  int64_t mtotal_i = mtotal;
+  void *margs[] = {&plans_dev, &ncx_i, &ncells_i, &mtotal_i, &models_dev};
   if (!graph) {
     if (hipMemcpyAsync(plans_dev, w->host_plans, table, hipMemcpyHostToDevice, stream) !=
         hipSuccess)
+      return DFR_E_DEVICE;
+    if (models && hipLaunchKernel(cell_models_batch_ptr(max_sord), mgrid, dim3(64), margs, 0,
+                                  stream) != hipSuccess)
       return DFR_E_DEVICE;
     if (launch_batch_f32(plans_dev, n, max_sord, G, interp, np, counter, grid, stream) !=
         hipSuccess)
@@ -263,7 +280,7 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
     BatchGraph *found = nullptr;
     for (auto &g : w->graphs)
       if (g.n == n && g.interp == interp && g.np == np && g.sord == max_sord && g.grid == grid &&
-          g.plans_dev == plans_dev && g.plans_host == w->host_plans &&
+          g.models == (int)models && g.plans_dev == plans_dev && g.plans_host == w->host_plans &&
           std::memcmp(&g.geom, &G, sizeof(G)) == 0)
         found = &g;
     if (!found) {
@@ -275,12 +292,23 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
       bg.np = np;
       bg.sord = max_sord;
       bg.grid = grid;
+      bg.models = (int)models;
       bg.plans_dev = plans_dev;
       bg.plans_host = w->host_plans;
       if (hipGraphCreate(&bg.graph, 0) != hipSuccess) return DFR_E_DEVICE;
-      hipGraphNode_t copy = nullptr, zero = nullptr, kern = nullptr;
+      hipGraphNode_t copy = nullptr, mod = nullptr, zero = nullptr, kern = nullptr;
       bool ok = hipGraphAddMemcpyNode1D(&copy, bg.graph, nullptr, 0, plans_dev, w->host_plans,
                                         table, hipMemcpyHostToDevice) == hipSuccess;
+      if (models) {
+        hipKernelNodeParams mp;
+        std::memset(&mp, 0, sizeof(mp));
+        mp.func = const_cast<void *>(cell_models_batch_ptr(max_sord));
+        mp.gridDim = mgrid;
+        mp.blockDim = dim3(64);
+        mp.sharedMemBytes = 0;
+        mp.kernelParams = margs;
+        ok = ok && hipGraphAddKernelNode(&mod, bg.graph, &copy, 1, &mp) == hipSuccess;
+      }
       int64_t one = 1;
       void *zargs[] = {&counter, &one};
       hipKernelNodeParams zp;
@@ -301,7 +329,7 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
       kp.blockDim = dim3(kThreads);
       kp.sharedMemBytes = lds_bytes;
       kp.kernelParams = kargs;
-      hipGraphNode_t deps[2] = {copy, zero};
+      hipGraphNode_t deps[2] = {models ? mod : copy, zero};
       ok = ok && hipGraphAddKernelNode(&kern, bg.graph, deps, 2, &kp) == hipSuccess;
       ok = ok && hipGraphInstantiate(&bg.exec, bg.graph, nullptr, nullptr, 0) == hipSuccess;
       if (!ok) {

@@ -38,7 +38,7 @@ void make_geom(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, int
 // here must be called with workspace_mutex() held.
 struct BatchGraph {
   TileGeom geom;
-  int n, interp, np, sord, grid;
+  int n, interp, np, sord, grid, models;
   void *plans_dev;
   void *plans_host;
   hipGraph_t graph;
@@ -63,8 +63,9 @@ void *workspace_buffer(Workspace *w, size_t bytes);
 void release_workspaces();
 
 // Reproject a batch in one persistent launch; `graph` replays a cached HIP
-// graph (frame-table copy, counter reset, persistent kernel).
+// graph (frame-table copy, per-cell models of every frame when `models`,
+// counter reset, persistent kernel).
 dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int interp, int np,
-                     int max_sord, hipStream_t stream, bool graph);
+                     int max_sord, bool models, hipStream_t stream, bool graph);
 
 }  // namespace dfr

@@ -4,7 +4,7 @@
 // builds in parallel.
 #pragma once
 
-#include "forward_body.hpp"
+#include "forward_tile.hpp"
 #include "launch.hpp"
 
 namespace dfr {
@@ -14,7 +14,7 @@ __global__ __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(NP >= 4 ? 4 : (INTERP == DFR_BILINEAR ? 8 : 6))))
 void reproject_tiles(FramePlan P, TileGeom G) {
   extern __shared__ float lds[];
-  __shared__ TileShared sh;
+  __shared__ FwdShared sh;
   forward_tile<INTERP, SORD, NP>(P, G, xcd_tile(blockIdx.x, G.n_tiles), lds, sh);
 }
 
@@ -30,7 +30,7 @@ __attribute__((amdgpu_waves_per_eu(NP >= 4 ? 4 : 5)))
 void reproject_batch(const FramePlan *__restrict__ plans, int n_frames, TileGeom G,
                      int *__restrict__ counter) {
   extern __shared__ float lds[];
-  __shared__ TileShared sh;
+  __shared__ FwdShared sh;
   const int total = n_frames * G.n_tiles;
   while (true) {
     if (threadIdx.x == 0) sh.item = atomicAdd(counter, 1);

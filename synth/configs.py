@@ -158,6 +158,27 @@ def pole(seed: int = 5, size: int = 8192, interp: int = BILINEAR) -> Case:
     return Case("pole", src, sw, tw, (h, w), interp, extra={"inverse_fit_resid_px": resid})
 
 
+def strong_sip(seed: int = 11, size: int = 256, order: int = 7, sigma: float = 1e-5,
+               interp: int = BILINEAR) -> Case:
+    """A stress map for the local cubic models: an inverse SIP made of the
+    terms of one high order only, sigma * N(0, 1) px at the frame edge per
+    term.  Its local quartic terms grow as the cube of the distance from
+    CRPIX, so with the default sigma cells near the centre admit a cubic
+    model within 1e-6 px and cells towards the edges do not."""
+    rng = np.random.default_rng(seed)
+    S = 0.5 * size
+    ap = np.zeros((order + 1, order + 1))
+    bp = np.zeros((order + 1, order + 1))
+    for p in range(order + 1):
+        q = order - p
+        ap[p, q] = rng.normal(0.0, sigma) * S / S ** order
+        bp[p, q] = rng.normal(0.0, sigma) * S / S ** order
+    src = star_field(size, size, 100.0, 5.0, max(1, size * size // 1300), seed, rng=rng)
+    sw = WcsParams.tan((150.0, 2.0), 2.85, 0.0, (size, size), ap=ap, bp=bp)
+    tw = WcsParams.tan((150.0, 2.0), 2.85, 0.5, (size, size), crpix_offset=(3.7, -2.2))
+    return Case("strong_sip", src, sw, tw, (size, size), interp)
+
+
 def demo(seed: int = 6, interp: int = BILINEAR) -> Case:
     rng = np.random.default_rng(seed)
     src = star_field(50, 50, 100.0, 5.0, 3, seed, rng=rng)

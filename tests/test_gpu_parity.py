@@ -116,6 +116,24 @@ def test_empty_and_uncovered(dfr, orc):
     assert torch.all(out == 0) and torch.all(fp == 0)
 
 
+def test_package_imported_before_torch():
+    """The library must run on torch's HIP runtime whatever the import order
+    (libdfr and torch both need libamdhip64.so.7)."""
+    import subprocess
+    import sys
+    code = ("import paper_2505_03932_amd as d\n"
+            "import torch\n"
+            "from synth import configs\n"
+            "c = configs.plain(size=96)\n"
+            "out, fp = d.reproject(torch.from_numpy(c.src).cuda(), c.src_wcs, c.tgt_wcs, c.out_shape)\n"
+            "torch.cuda.synchronize()\n"
+            "print('ok', float(fp.sum()))\n")
+    root = __file__.rsplit("/tests/", 1)[0]
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=180)
+    assert r.returncode == 0 and r.stdout.startswith("ok"), r.stderr[-2000:]
+
+
 def test_identity_nearest_bit_exact(dfr):
     c = configs.plain(size=130)
     out, fp = dfr.reproject(torch.from_numpy(c.src).cuda(), c.src_wcs, c.src_wcs, c.src.shape,
@@ -135,6 +153,43 @@ def test_tile_shapes_bit_identical(dfr):
                 ref = (out.clone(), fp.clone())
             else:
                 assert torch.equal(out, ref[0]) and torch.equal(fp, ref[1]), (interp, t)
+
+
+@pytest.mark.parametrize("interp", [0, 1, 2])
+def test_anchor_chain_form(dfr, orc, interp):
+    """The FP32 chain evaluated per pixel from FP64 anchors (no cell models)."""
+    c = configs.sip3(scale=0.1, interp=interp)
+    check_case(dfr, orc, c.src, c.src_wcs, c.tgt_wcs, c.out_shape, interp, precision="f32_anchor")
+
+
+def test_models_and_anchor_chain_agree(dfr):
+    """Positions of the two FP32 forms differ by their FP32 rounding only."""
+    c = configs.sip3(scale=0.15)
+    src = torch.from_numpy(c.src).cuda()
+    _, _, pm = dfr.reproject(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bilinear",
+                             debug_positions=True)
+    _, _, pa = dfr.reproject(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bilinear",
+                             debug_positions=True, precision="f32_anchor")
+    d = (pm - pa).abs()
+    ok = torch.isfinite(d)
+    assert ok.float().mean() > 0.95
+    assert d[ok].max().item() < 2e-5
+
+
+@pytest.mark.parametrize("interp", [0, 1, 2])
+def test_mixed_model_and_anchor_cells(dfr, orc, interp):
+    """A map whose central cells have certified models and whose outer cells
+    do not: tiles mix both kinds of cell."""
+    c = configs.strong_sip(interp=interp)
+    check_case(dfr, orc, c.src, c.src_wcs, c.tgt_wcs, c.out_shape, interp)
+    src = torch.from_numpy(c.src).cuda()
+    ref = None
+    for t in range(1, 13):
+        out, fp = dfr.reproject(src, c.src_wcs, c.tgt_wcs, c.out_shape, INTERPS[interp], tile=t)
+        if ref is None:
+            ref = (out.clone(), fp.clone())
+        else:
+            assert torch.equal(out, ref[0]) and torch.equal(fp, ref[1]), t
 
 
 @pytest.mark.parametrize("precision", ["f64", "trig"])
