@@ -268,14 +268,18 @@ __device__ __forceinline__ void stage_box(const FramePlan &P, int bi0, int bj0, 
   }
 }
 
+// Output stores are streaming (non-temporal): the output is written once
+// and never read back by the kernel, so it should not evict the source
+// footprint other tiles still read from L2 and the last-level cache.
 __device__ __forceinline__ void store_run(float *__restrict__ base, int64_t off, int x, int out_w,
                                           bool vec, const float v[kRun]) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
   if (vec && x + kRun <= out_w) {
-    *reinterpret_cast<float4 *>(base + off) = make_float4(v[0], v[1], v[2], v[3]);
+    __builtin_nontemporal_store((f4v){v[0], v[1], v[2], v[3]}, reinterpret_cast<f4v *>(base + off));
   } else {
 #pragma unroll
     for (int e = 0; e < kRun; ++e)
-      if (x + e < out_w) base[off + e] = v[e];
+      if (x + e < out_w) __builtin_nontemporal_store(v[e], base + off + e);
   }
 }
 
