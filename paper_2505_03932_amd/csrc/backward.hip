@@ -118,21 +118,26 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
     tile_positions<INTERP, SORD, TSIP, NP>(P, G, sh, c, T);
     const int bw = T.empty ? 0 : T.bi1 - T.bi0 + 1;
     const int bh = T.empty ? 0 : T.bj1 - T.bj0 + 1;
-    const bool use_lds = !T.empty && 2 * (int64_t)bw * bh <= (int64_t)G.lds_cap;
+    const int lp = lds_pitch(bw);  // padded row stride (bank spread)
+    const bool want_src = gsrc != nullptr;
+    const bool use_lds = !T.empty && (want_src ? 2 : 1) * (int64_t)lp * bh <= (int64_t)G.lds_cap;
     float *vals = lds;
-    float *gacc = lds + (use_lds ? bw * bh : 0);
+    float *gacc = lds + (use_lds ? lp * bh : 0);
     if (use_lds) {
-      stage_box(P, T.bi0, T.bj0, bw, bh, vals);
-      for (int i = tid; i < bw * bh; i += kThreads) gacc[i] = 0.0f;
+      stage_box(P, T.bi0, T.bj0, bw, bh, lp, vals);
+      if (want_src)
+        for (int i = tid; i < lp * bh; i += kThreads) gacc[i] = 0.0f;
     }
     __syncthreads();
     const int W = P.src_w, Hs = P.src_h;
     const int bi0 = T.bi0, bj0 = T.bj0;
-    auto fetch_lds = [&](int i, int j) -> float { return vals[(j - bj0) * bw + (i - bi0)]; };
+    auto fetch_lds = [&](int i, int j) -> float { return vals[(j - bj0) * lp + (i - bi0)]; };
     auto fetch_glb = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
-    auto scat_lds = [&](int i, int j, float v) { atomicAdd(&gacc[(j - bj0) * bw + (i - bi0)], v); };
+    auto scat_lds = [&](int i, int j, float v) {
+      if (want_src) atomicAdd(&gacc[(j - bj0) * lp + (i - bi0)], v);
+    };
     auto scat_glb = [&](int i, int j, float v) {
-      if (gsrc) atomicAdd(&gsrc[(int64_t)j * gpitch + i], v);
+      if (want_src) atomicAdd(&gsrc[(int64_t)j * gpitch + i], v);
     };
     const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
     const float S_s = (float)P.s_scale;
@@ -202,7 +207,7 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
       const int wave = tid >> 6, lane = tid & 63;
       for (int r = wave; r < bh; r += kThreads / 64)
         for (int col = lane; col < bw; col += 64) {
-          float v = gacc[r * bw + col];
+          float v = gacc[r * lp + col];
           if (v != 0.0f) atomicAdd(&gsrc[(int64_t)(bj0 + r) * gpitch + bi0 + col], v);
         }
     }
@@ -210,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
   // per-wave, then per-group sums of the WCS terms (skipped tiles give 0)
 #pragma unroll
   for (int s = 0; s < NS; ++s) {
-    float v = wave_sum(acc[s]);
+    float v = wave_sum_dpp(acc[s]);
     if ((tid & 63) == 0) wsum[tid >> 6][s] = v;
   }
   __syncthreads();

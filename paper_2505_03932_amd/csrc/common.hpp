@@ -464,6 +464,31 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Sum over the wave, returned uniform: an inclusive scan within each row of
+// 16 lanes (DPP row_shr 1, 2, 4, 8), then the row totals carried across the
+// rows (DPP row_bcast 15 and 31), so lane 63 holds the total.  Plain VALU
+// instructions (a shuffle tree would go through the LDS crossbar), in a
+// fixed order.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int s = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false);
+  return v + __builtin_bit_cast(float, s);
+}
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+  v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+  v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+  v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// LDS row stride for a staged box of width bw: bw rounded up to 1 mod 4, so
+// the 4 rows x 16 runs of 4 pixels a wave touches at once fall in distinct
+// banks (rows shift the bank by 1, 2, 3 instead of a multiple of 4).
+__host__ __device__ __forceinline__ int lds_pitch(int bw) { return bw + ((1 - bw) & 3); }
+
 // Work-group index -> tile index, so that the ~n/8 consecutive (spatially
 // adjacent) tiles land on the same XCD: work-groups are dealt round-robin
 // over the 8 XCDs, each with its own L2, and neighbouring tiles share

@@ -258,12 +258,12 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
 // stride bw) with one wave per row and consecutive lanes on consecutive
 // columns.  The caller synchronises.
 __device__ __forceinline__ void stage_box(const FramePlan &P, int bi0, int bj0, int bw, int bh,
-                                          float *__restrict__ lds) {
+                                          int lp, float *__restrict__ lds) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const float *__restrict__ s0 = P.src + (int64_t)bj0 * P.pitch + bi0;
   for (int r = wave; r < bh; r += kThreads / 64) {
     const float *__restrict__ sr = s0 + (int64_t)r * P.pitch;
-    float *__restrict__ lr = lds + r * bw;
+    float *__restrict__ lr = lds + r * lp;
     for (int col = lane; col < bw; col += 64) lr[col] = sr[col];
   }
 }

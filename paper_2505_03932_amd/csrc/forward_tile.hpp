@@ -40,10 +40,10 @@ struct FwdShared {
 };
 
 // Stage rows [bj0, bj0+bh) x columns [bi0, bi0+bw) of the source into LDS
-// (row stride bw) with asynchronous DMA: one wave per row, 64 columns per
+// (row stride lp) with asynchronous DMA: one wave per row, 64 columns per
 // instruction, lanes past the row end masked off.
 __device__ __forceinline__ void dma_box(const FramePlan &P, int bi0, int bj0, int bw, int bh,
-                                        float *__restrict__ lds) {
+                                        int lp, float *__restrict__ lds) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const float *__restrict__ s0 = P.src + (int64_t)bj0 * P.pitch + bi0;
 #pragma unroll 1
@@ -52,7 +52,7 @@ __device__ __forceinline__ void dma_box(const FramePlan &P, int bi0, int bj0, in
 #pragma unroll 1
     for (int c0 = 0; c0 < bw; c0 += 64) {
       if (c0 + lane < bw)
-        __builtin_amdgcn_global_load_lds(sr + c0 + lane, lds + r * bw + c0, 4, 0, 0);
+        __builtin_amdgcn_global_load_lds(sr + c0 + lane, lds + r * lp + c0, 4, 0, 0);
     }
   }
 }
@@ -189,10 +189,11 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   const int bi0 = max(bu0, 0), bi1 = min(bu1, W - 1), bj0 = max(bu2, 0), bj1 = min(bu3, Hs - 1);
   const bool box_ok = sh.box_ok && bi0 <= bi1 && bj0 <= bj1;
   const int bw = box_ok ? bi1 - bi0 + 1 : 0, bh = box_ok ? bj1 - bj0 + 1 : 0;
-  const bool use_lds = box_ok && (int64_t)bw * bh <= (int64_t)G.lds_cap;
+  const int lp = lds_pitch(bw);  // padded row stride (bank spread)
+  const bool use_lds = box_ok && (int64_t)lp * bh <= (int64_t)G.lds_cap;
   const bool interior = use_lds && sh.cells_ok && P.t_order == 0 && bu0 == bi0 && bu1 == bi1 &&
                         bu2 == bj0 && bu3 == bj1 && x0 + TW <= G.out_w && y0 + TH <= G.out_h;
-  if (use_lds) dma_box(P, bi0, bj0, bw, bh, lds);
+  if (use_lds) dma_box(P, bi0, bj0, bw, bh, lp, lds);
 
   // ---- 3. positions: the cell's model, or FP32 offsets from its anchor
   const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
@@ -297,8 +298,8 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
         tap_origin<INTERP>(rx[k][e], abx[k], i0, t_);
         tap_origin<INTERP>(ry[k][e], aby[k], j0, s_);
         // i0, j0 >= 0 inside the box: one 24-bit multiply-add per pixel
-        const float *__restrict__ b = lds + __umul24(j0, bw) + i0;
-        auto fl = [&](int i, int j) -> float { return b[j * bw + i]; };
+        const float *__restrict__ b = lds + __umul24(j0, lp) + i0;
+        auto fl = [&](int i, int j) -> float { return b[j * lp + i]; };
         if constexpr (INTERP == DFR_NEAREST) {
           o[e] = b[0];
         } else if constexpr (INTERP == DFR_BILINEAR) {
@@ -319,7 +320,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   }
   // general path: source coordinates, zero padding, footprint normalisation;
   // taps come from LDS when the pixel's in-image taps are inside the box
-  auto fl = [&](int i, int j) -> float { return lds[__umul24(j - bj0, bw) + (i - bi0)]; };
+  auto fl = [&](int i, int j) -> float { return lds[__umul24(j - bj0, lp) + (i - bi0)]; };
   auto fg = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
 #pragma unroll
   for (int k = 0; k < NP; ++k) {

@@ -217,8 +217,9 @@ int estimate_lds_floats(const FramePlan &P, int32_t out_h, int32_t out_w, const 
       double J[4];
       if (!jacobian_at(P, x, y, J)) continue;
       any = true;
-      // the kernel's box: extreme tap origins grown by the support and 2 px
-      double bw = std::fabs(J[0]) * (s.width - 1) + std::fabs(J[1]) * (s.height - 1) + support + 6.0;
+      // the kernel's box: extreme tap origins grown by the support and 2 px,
+      // rows padded by up to 3 floats (LDS bank spread)
+      double bw = std::fabs(J[0]) * (s.width - 1) + std::fabs(J[1]) * (s.height - 1) + support + 9.0;
       double bh = std::fabs(J[2]) * (s.width - 1) + std::fabs(J[3]) * (s.height - 1) + support + 6.0;
       best = std::max(best, bw * bh);
     }
