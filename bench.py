@@ -5,15 +5,24 @@ Headline: output Mpix/s of the bilinear forward reprojection of the
 6000x4000 frame with SIP A/B order 3 and fitted inverse AP/BP order 4
 (target 6000x4000 TAN, 40 px offset, rotated 0.3 deg), output and footprint
 float32, inputs resident in HBM.  One step = one full forward pass over the
-frame (host set-up + one kernel launch through the C ABI).
+frame through the C ABI: host set-up, the per-cell position-model prepass and
+the tile kernel (two launches on the caller's stream).
 
-Beside it: the roofline of that kernel (algorithmic bytes per launch over the
-launch's average duration from HIP events on its stream, against 8 TB/s),
+Beside it: the roofline of the step (algorithmic bytes per step over the
+step's average duration from HIP events on its stream, against 8 TB/s; the
+step is the two launches, so this bounds the tile kernel's own fraction from
+below), the HBM traffic the committed rocprofv3 PMC summary measured,
 the FP64 CPU oracle timed on this host, and the other forms of the path
 (nearest and bicubic, the FP64 and trigonometric forms, forward+backward on
 the 2048^2 alignment case, the 64-frame batch, the +89.5 deg precision case).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras]
+                    [--no-cpu-baseline] [--calibrate-copy]
+
+--calibrate-copy adds, after the timed steps, three plain device copies of a
+512,000,000-byte buffer, each from a source pushed out of the caches by a
+512 MB fill just before it: the PMC runs read FETCH_SIZE and WRITE_SIZE of
+that known-size copy to scale the counters.
 """
 from __future__ import annotations
 
@@ -48,16 +57,16 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(name: str):
-    """HBM traffic of the headline kernel from the committed rocprofv3 PMC
-    summary, if it was taken on the current kernel sources."""
+def stored_profile(name: str, tag: str):
+    """A record of a committed rocprofv3 summary (`<!--tag {json}-->`), if it
+    was taken on the current kernel sources."""
     p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     with open(p) as f:
         for line in f:
-            if line.startswith("<!--traffic "):
-                d = json.loads(line[len("<!--traffic "):].rsplit("-->", 1)[0])
+            if line.startswith(f"<!--{tag} "):
+                d = json.loads(line[len(f"<!--{tag} "):].rsplit("-->", 1)[0])
                 if d.get("kernel_source_hash") == kernel_source_hash():
                     return d
     return None
@@ -151,6 +160,11 @@ def extra_forms(dfr, case, steps):
         ms, _ = time_steps(fr.step, steps, 2)
         res[f"sip3_{interp}"] = {"mpix_s": round(npx / ms / 1e3, 1), "ms": round(ms, 4)}
         del fr
+    fr = Frame(dfr, case.src, case.src_wcs, case.tgt_wcs, case.out_shape, "bilinear",
+               precision="f32_anchor")
+    ms, _ = time_steps(fr.step, steps, 2)
+    res["sip3_bilinear_f32_anchor"] = {"mpix_s": round(npx / ms / 1e3, 1), "ms": round(ms, 4)}
+    del fr
     for prec in ("f64", "trig"):
         fr = Frame(dfr, case.src, case.src_wcs, case.tgt_wcs, case.out_shape, "bilinear",
                    precision=prec, n_sets=1)
@@ -247,6 +261,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the reprojection on a single MI355X "
@@ -270,14 +285,32 @@ def main():
                                     "bilinear")
     alg_bytes = 8 * npx + 4 * touched
     achieved = alg_bytes / ms / 1e6  # GB/s
-    traffic = stored_traffic("reproject_sip3_bilinear_pmc.md")
+    traffic = stored_profile("reproject_sip3_bilinear_pmc.md", "traffic")
+    split = stored_profile("reproject_sip3_bilinear_kernel_trace.md", "split")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (traffic or {}).get("bytes_per_launch"),
-            "alg_bytes_per_launch": alg_bytes, "kernel_ms": round(ms, 5),
+            "alg_bytes_per_launch": alg_bytes, "step_ms": round(ms, 5),
+            "launches": "cell_models_kernel + reproject_tiles (HIP events around both)",
             "touched_src_px": touched}
+    if split:
+        # the tile kernel alone, from the committed kernel trace of this command
+        roof["trace_tiles_us"] = split["tiles_us"]
+        roof["trace_models_us"] = split["models_us"]
+        roof["tiles_frac_from_trace"] = round(alg_bytes / (split["tiles_us"] * 1e3) / HBM_PEAK_GBS, 4)
     del frame
     torch.cuda.empty_cache()
+    if args.calibrate_copy:
+        n = 128_000_000  # 512,000,000 bytes, twice the last-level cache
+        a = torch.full((n,), 1.0, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        evict = torch.empty_like(a)
+        for _ in range(3):
+            evict.fill_(2.0)
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b, evict
+        torch.cuda.empty_cache()
 
     forms = {}
     if not args.no_extras:
