@@ -65,6 +65,7 @@ struct FramePlan {
   int32_t series;           // 1: |k.d| < 1e-3 over the frame, 1/(1+e) = 1 - e + e^2
   int32_t pad_;
   const CellModel *models;  // device table of per-cell position models, or null
+  int32_t *reach;           // batch: the frame's reach box of cells (see kReachBig), or null
   double tA[kMaxCoef], tB[kMaxCoef];   // FP64 coefficients, packed by tri9
   double sA[kMaxCoef], sB[kMaxCoef];
   float ftA[kMaxCoef], ftB[kMaxCoef];  // FP32, scaled: c * S^(p+q)
@@ -298,6 +299,11 @@ __device__ __forceinline__ bool position_f64_ct(const FramePlan &P, double x, do
   ys = V + dV + P.scr[1];
   return isfinite(xs) && isfinite(ys);
 }
+
+// Reach box of a frame in cell units, encoded so that all zeros means
+// "empty": {max(kReachBig - cx), max(cx + 1), max(kReachBig - cy), max(cy + 1)}
+// over the cells that may reach the source.
+constexpr int32_t kReachBig = 1 << 24;
 
 constexpr double kFar = 268435456.0;  // 2^28: anchors beyond this are out of any image
 

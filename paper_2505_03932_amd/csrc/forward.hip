@@ -47,16 +47,58 @@ __global__ __launch_bounds__(64) void cell_models_batch_kernel(const FramePlan *
                                                               int ncx, int ncells, int64_t total,
                                                               CellModel *__restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (i >= total) return;
-  const int frame = (int)(i / ncells), c = (int)(i - (int64_t)frame * ncells);
+  const bool active = i < total;
+  const int frame = active ? (int)(i / ncells) : 0;
+  const int c = (int)(i - (int64_t)frame * ncells);
   const int cy = c / ncx, cx = c - cy * ncx;
   // the frame table is read-only here: scalar loads through the constant
   // address space
   using ConstPlan = const __attribute__((address_space(4))) FramePlan;
   ConstPlan *cp = (ConstPlan *)(plans + frame);
-  CellModel M;
-  cell_model<SORD>(*(const FramePlan *)cp, cx, cy, M);
-  out[i] = M;
+  const FramePlan &P = *(const FramePlan *)cp;
+  int reach = 0;
+  if (active) {
+    CellModel M;
+    cell_model<SORD>(P, cx, cy, M);
+    out[i] = M;
+    // can any pixel of the cell have a tap inside the source?  From the
+    // model's range over the whole cell, grown by 4 px (more than any tap
+    // support and the tile kernel's guard); without a model: assume so
+    reach = 1;
+    if (P.src_w <= 0 || P.src_h <= 0) {
+      reach = 0;
+    } else if (M.certified) {
+      const float h = (float)kHalfCell;
+      const float rx = (fabsf(M.mx[4]) + fabsf(M.mx[1])) * h + M.ex + 4.0f;
+      const float ry = (fabsf(M.my[4]) + fabsf(M.my[1])) * h + M.ey + 4.0f;
+      const float xc = (float)M.bx + M.mx[0], yc = (float)M.by + M.my[0];
+      reach = (xc + rx >= 0.0f && xc - rx <= (float)(P.src_w - 1) && yc + ry >= 0.0f &&
+               yc - ry <= (float)(P.src_h - 1)) ? 1 : 0;
+    }
+  }
+  if (P.reach == nullptr) return;
+  // the wave's reaching cells merged first (usually all of one frame)
+  int v0 = reach ? kReachBig - cx : 0, v1 = reach ? cx + 1 : 0;
+  int v2 = reach ? kReachBig - cy : 0, v3 = reach ? cy + 1 : 0;
+  const int f0 = __builtin_amdgcn_readfirstlane(frame);
+  const bool one_frame = __ballot(frame != f0) == 0ull;
+  if (one_frame) {
+    v0 = wave_max(v0);
+    v1 = wave_max(v1);
+    v2 = wave_max(v2);
+    v3 = wave_max(v3);
+    if (threadIdx.x == 0 && v1 > 0) {
+      atomicMax(P.reach + 0, v0);
+      atomicMax(P.reach + 1, v1);
+      atomicMax(P.reach + 2, v2);
+      atomicMax(P.reach + 3, v3);
+    }
+  } else if (reach) {
+    atomicMax(P.reach + 0, v0);
+    atomicMax(P.reach + 1, v1);
+    atomicMax(P.reach + 2, v2);
+    atomicMax(P.reach + 3, v3);
+  }
 }
 
 const void *cell_models_batch_ptr(int sord) {

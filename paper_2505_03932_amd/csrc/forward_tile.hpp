@@ -57,6 +57,52 @@ __device__ __forceinline__ void dma_box(const FramePlan &P, int bi0, int bj0, in
   }
 }
 
+// A tile no pixel of which reaches the source: output "uncovered" (0, or
+// NaN with nan_outside) and footprint 0.
+template <int NP>
+__device__ __forceinline__ void tile_uncovered(const FramePlan &P, const TileGeom &G, int tile) {
+  const int lg = G.txt_log2;
+  const int TW = kRun << lg, RP = kThreads >> lg, TH = RP * NP;
+  const int trow = tile / G.tiles_x;
+  const int x0 = (tile - trow * G.tiles_x) * TW, y0 = trow * TH;
+  const int ty = threadIdx.x >> lg, xr = x0 + (threadIdx.x & ((1 << lg) - 1)) * kRun;
+  const bool vec = vector_stores_ok(P, G);
+  const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
+  float zo[kRun], zf[kRun];
+#pragma unroll
+  for (int e = 0; e < kRun; ++e) {
+    zo[e] = miss;
+    zf[e] = 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    const int y = y0 + ty + k * RP;
+    if (y >= G.out_h || xr >= G.out_w) continue;
+    const int64_t off = (int64_t)y * G.out_w + xr;
+    store_run(P.out, off, xr, G.out_w, vec, zo);
+    if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, zf);
+  }
+}
+
+// Whether tile `tile` lies outside the frame's reach box (cells that may
+// reach the source, recorded by the batch model prepass): then it is
+// uncovered without looking at its cells.
+template <int NP>
+__device__ __forceinline__ bool tile_out_of_reach(const FramePlan &P, const TileGeom &G, int tile) {
+  if (P.reach == nullptr) return false;
+  using ConstI = const __attribute__((address_space(4))) int32_t;
+  ConstI *r = (ConstI *)P.reach;
+  const int r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+  if (r1 == 0) return true;  // no cell of the frame reaches its source
+  const int lg = G.txt_log2;
+  const int TW = kRun << lg, TH = (kThreads >> lg) * NP;
+  const int trow = tile / G.tiles_x;
+  const int x0 = (tile - trow * G.tiles_x) * TW, y0 = trow * TH;
+  const int cx0 = x0 >> kCellLog2, cx1 = (x0 + TW - 1) >> kCellLog2;
+  const int cy0 = y0 >> kCellLog2, cy1 = (y0 + TH - 1) >> kCellLog2;
+  return cx1 < kReachBig - r0 || cx0 >= r1 || cy1 < kReachBig - r2 || cy0 >= r3;
+}
+
 // The target SIP is compiled only into the run-time-order variant (the
 // launcher uses it whenever the target WCS has A/B).
 template <int INTERP, int SORD, int NP>
@@ -166,21 +212,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   const bool vec = vector_stores_ok(P, G);
   const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
   if (!sh.touch && G.allow_skip) {
-    // no pixel of the tile reaches the source
-    float zo[kRun], zf[kRun];
-#pragma unroll
-    for (int e = 0; e < kRun; ++e) {
-      zo[e] = miss;
-      zf[e] = 0.0f;
-    }
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      const int y = y0 + ty + k * RP;
-      if (y >= G.out_h || xr >= G.out_w) continue;
-      const int64_t off = (int64_t)y * G.out_w + xr;
-      store_run(P.out, off, xr, G.out_w, vec, zo);
-      if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, zf);
-    }
+    tile_uncovered<NP>(P, G, tile);
     return;
   }
 

@@ -227,16 +227,20 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
   if (!w) return DFR_E_DEVICE;
   const int n = (int)plans.size();
   const size_t table = (size_t)n * sizeof(FramePlan);
-  // counter | frame table | per-frame model tables (when used)
+  // counter + reach boxes (4 ints per frame, zeroed together) | frame table |
+  // per-frame model tables (when used)
   models = models && plans[0].t_order == 0;
   const int ncx = (G.out_w + kCell - 1) / kCell, ncy = (G.out_h + kCell - 1) / kCell;
   const int64_t ncells = (int64_t)ncx * ncy;
-  const size_t mofs = (256 + table + 255) & ~(size_t)255;
+  const int64_t nzero = 4 + 4 * (int64_t)n;  // counter padded to 16 bytes, then the boxes
+  const size_t tofs = ((size_t)nzero * 4 + 255) & ~(size_t)255;
+  const size_t mofs = (tofs + table + 255) & ~(size_t)255;
   const size_t mbytes = models ? (size_t)n * ncells * sizeof(CellModel) : 0;
   char *dev = static_cast<char *>(workspace_buffer(w, mofs + mbytes));
   if (!dev) return DFR_E_NOMEM;
   int *counter = reinterpret_cast<int *>(dev);
-  FramePlan *plans_dev = reinterpret_cast<FramePlan *>(dev + 256);
+  int32_t *reach = reinterpret_cast<int32_t *>(dev) + 4;
+  FramePlan *plans_dev = reinterpret_cast<FramePlan *>(dev + tofs);
   CellModel *models_dev = models ? reinterpret_cast<CellModel *>(dev + mofs) : nullptr;
   // the previous batch on this stream must have copied the staged table
   if (w->staged_pending) {
@@ -253,7 +257,10 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
     w->host_cap = n;
   }
   std::memcpy(w->host_plans, plans.data(), table);
-  for (int i = 0; i < n; ++i) w->host_plans[i].models = models ? models_dev + i * ncells : nullptr;
+  for (int i = 0; i < n; ++i) {
+    w->host_plans[i].models = models ? models_dev + i * ncells : nullptr;
+    w->host_plans[i].reach = models ? reach + 4 * i : nullptr;
+  }
   int dev_id = 0, cus = 0;
   if (hipGetDevice(&dev_id) != hipSuccess) return DFR_E_DEVICE;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id) != hipSuccess ||
@@ -270,6 +277,8 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
     if (hipMemcpyAsync(plans_dev, w->host_plans, table, hipMemcpyHostToDevice, stream) !=
         hipSuccess)
       return DFR_E_DEVICE;
+    // counter and reach boxes start at zero; the prepass then records the boxes
+    if (launch_zero_i32(counter, nzero, stream) != hipSuccess) return DFR_E_DEVICE;
     if (models && hipLaunchKernel(cell_models_batch_ptr(max_sord), mgrid, dim3(64), margs, 0,
                                   stream) != hipSuccess)
       return DFR_E_DEVICE;
@@ -309,8 +318,8 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
         mp.kernelParams = margs;
         ok = ok && hipGraphAddKernelNode(&mod, bg.graph, &copy, 1, &mp) == hipSuccess;
       }
-      int64_t one = 1;
-      void *zargs[] = {&counter, &one};
+      int64_t nz = nzero;
+      void *zargs[] = {&counter, &nz};
       hipKernelNodeParams zp;
       std::memset(&zp, 0, sizeof(zp));
       zp.func = const_cast<void *>(zero_i32_kernel_ptr());
@@ -331,6 +340,8 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
       kp.kernelParams = kargs;
       hipGraphNode_t deps[2] = {models ? mod : copy, zero};
       ok = ok && hipGraphAddKernelNode(&kern, bg.graph, deps, 2, &kp) == hipSuccess;
+      // the prepass records the reach boxes: it runs after they are zeroed
+      if (models) ok = ok && hipGraphAddDependencies(bg.graph, &zero, &mod, 1) == hipSuccess;
       ok = ok && hipGraphInstantiate(&bg.exec, bg.graph, nullptr, nullptr, 0) == hipSuccess;
       if (!ok) {
         (void)hipGraphDestroy(bg.graph);

@@ -18,6 +18,8 @@ void reproject_tiles(FramePlan P, TileGeom G) {
   forward_tile<INTERP, SORD, NP>(P, G, xcd_tile(blockIdx.x, G.n_tiles), lds, sh);
 }
 
+constexpr int kBatchChunk = 16;  // (frame, tile) items claimed per atomic
+
 // Batched reprojection: many source frames of uneven sizes onto one target
 // grid in one persistent launch (the paper's stacking use case, section 1).
 // Work items are (frame, tile) pairs handed out by an atomic counter, so
@@ -32,8 +34,17 @@ void reproject_batch(const FramePlan *__restrict__ plans, int n_frames, TileGeom
   extern __shared__ float lds[];
   __shared__ FwdShared sh;
   const int total = n_frames * G.n_tiles;
+  // thread 0 claims kBatchChunk consecutive items per atomic (one counter
+  // round trip per chunk, not per item) and hands them out one by one
+  int next = 0, end = 0;
   while (true) {
-    if (threadIdx.x == 0) sh.item = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) {
+      if (next >= end) {
+        next = atomicAdd(counter, kBatchChunk);
+        end = next + kBatchChunk;
+      }
+      sh.item = next++;
+    }
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(sh.item);
     if (item >= total) break;  // every wave sees the same item: the group leaves together
@@ -42,8 +53,12 @@ void reproject_batch(const FramePlan *__restrict__ plans, int n_frames, TileGeom
     // written during the launch, so its fields can be scalar (SGPR) loads
     using ConstPlan = const __attribute__((address_space(4))) FramePlan;
     ConstPlan *cp = (ConstPlan *)(plans + frame);
-    forward_tile<INTERP, SORD, NP>(*(const FramePlan *)cp, G, item - frame * G.n_tiles, lds,
-                                   sh);
+    const FramePlan &P = *(const FramePlan *)cp;
+    const int tile = item - frame * G.n_tiles;
+    if (tile_out_of_reach<NP>(P, G, tile))
+      tile_uncovered<NP>(P, G, tile);  // most of a frame that covers part of the grid
+    else
+      forward_tile<INTERP, SORD, NP>(P, G, tile, lds, sh);
     __syncthreads();
   }
 }
