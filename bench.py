@@ -201,7 +201,8 @@ def extra_grad(dfr, steps):
 
 
 def extra_batch(dfr, steps):
-    """64 uneven frames onto one 8192^2 grid in one graph-replayed launch."""
+    """64 uneven frames onto one 8192^2 grid in one graph-replayed launch, and
+    the same frames coadded (footprint-weighted sums, no per-frame output)."""
     import torch
     from synth import configs
     t0 = time.perf_counter()
@@ -222,7 +223,19 @@ def extra_batch(dfr, steps):
     res = {"batch64_8192_bilinear": {"mpix_s": round(npx / ms / 1e3, 1), "ms": round(ms, 3),
                                      "gbs_alg": round(byts / ms / 1e6, 1),
                                      "hbm_frac": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)}}
-    del outs, fps, srcs
+    del outs, fps
+    torch.cuda.empty_cache()
+    # the same stack coadded: sources read once, three target images written
+    swf = torch.empty((oh, ow), dtype=torch.float32, device="cuda")
+    sf = torch.empty_like(swf)
+    ms_c, _ = time_steps(lambda: dfr.coadd_batch(srcs, c.src_wcs, c.tgt_wcs, c.out_shape,
+                                                 "bilinear", sum_wf=swf, sum_f=sf),
+                         max(2, steps // 2), 1)
+    byts_c = src_bytes + 3 * oh * ow * 4
+    res["coadd64_8192_bilinear"] = {"mpix_s": round(npx / ms_c / 1e3, 1), "ms": round(ms_c, 3),
+                                    "gbs_alg": round(byts_c / ms_c / 1e6, 1),
+                                    "hbm_frac": round(byts_c / ms_c / 1e6 / HBM_PEAK_GBS, 4)}
+    del swf, sf, srcs
     torch.cuda.empty_cache()
     return res
 

@@ -137,6 +137,29 @@ dfr_status dfr_reproject_batch(int32_t n, const dfr_frame *frames, const dfr_wcs
                                float *const *outs, float *const *footprints,
                                const dfr_options *opt, void *stream);
 
+/* Coadd (stack) n frames onto one target grid: the paper's motivating use of
+ * reprojection, combining sub-exposures on a common grid (section 1), with
+ * each frame weighted by its footprint (the per-pixel normalisation of
+ * section 3.1).  With out_i and F_i what dfr_reproject gives for frame i,
+ * per target pixel, over the frames with F_i > 0 there:
+ *   sum_wf  device [out_h][out_w] float32: sum of out_i * F_i
+ *   sum_f   device [out_h][out_w] float32: sum of F_i
+ *   coadd   device [out_h][out_w] float32, nullable: sum_wf / sum_f where
+ *           sum_f > 0, else 0 (NaN with opt->nan_outside)
+ * The sums are FP32, accumulated in frame order (fused multiply-add), so
+ * the result is deterministic and independent of the tile shape.  With
+ * accumulate != 0 the sums start from the values already in sum_wf and
+ * sum_f (a stack too large for one call is built by several; the result is
+ * then bit-identical to one call over all frames in the same order).  The
+ * three outputs must not overlap each other or any source.  n = 0 is an
+ * empty stack.  opt->tile chooses the tile (0: a default); no per-frame
+ * output is written, so the per-frame image traffic of the batch is gone:
+ * each source is read about once and each target pixel written once. */
+dfr_status dfr_coadd_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_wcs,
+                           int32_t out_h, int32_t out_w, dfr_interp interp, float *sum_wf,
+                           float *sum_f, float *coadd, int32_t accumulate,
+                           const dfr_options *opt, void *stream);
+
 /* Number of source-WCS gradient entries dfr_reproject_backward writes:
  * crval(2), crpix(2), cd(4), ap[(ap_order+1)^2], bp[(bp_order+1)^2]. */
 int64_t dfr_wcs_grad_size(const dfr_wcs *src_wcs);

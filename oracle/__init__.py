@@ -169,6 +169,34 @@ def reproject(src, src_wcs, tgt_wcs, out_shape=None, interp="bilinear", cubic_a=
     return (out, fp, pos) if want_pos else (out, fp)
 
 
+def coadd(srcs, src_wcss, tgt_wcs, out_shape, interp="bilinear", cubic_a=-0.5, rows=None,
+          threads=0, nan_outside=False):
+    """Footprint-weighted stack of frames on the target rows ``rows``.
+
+    The stacking use of reprojection (section 1) written out from the
+    per-frame result of section 3.1: with out_i, F_i the reprojection of
+    frame i, sum_wf = sum of out_i * F_i and sum_f = sum of F_i over the
+    frames with F_i > 0 (an uncovered pixel has F_i = 0 and contributes
+    nothing), and coadd = sum_wf / sum_f where sum_f > 0, else 0 (NaN with
+    nan_outside).  Returns (coadd, sum_wf, sum_f), float64 [len(rows), W]."""
+    oh, ow = out_shape
+    n = oh if rows is None else len(rows)
+    sum_wf = np.zeros((n, ow))
+    sum_f = np.zeros((n, ow))
+    for src, w in zip(srcs, src_wcss):
+        if src.size == 0:
+            continue
+        out, fp = reproject(src, w, tgt_wcs, out_shape, interp, cubic_a, rows=rows,
+                            threads=threads)
+        cov = fp > 0
+        sum_wf[cov] += out[cov] * fp[cov]
+        sum_f[cov] += fp[cov]
+    img = np.full((n, ow), np.nan if nan_outside else 0.0)
+    cov = sum_f > 0
+    img[cov] = sum_wf[cov] / sum_f[cov]
+    return img, sum_wf, sum_f
+
+
 def interp_at(src, pos, interp="bilinear", cubic_a=-0.5):
     """Interpolate ``src`` at source positions pos [n, 2].
 

@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "DFR_OK", 1: "DFR_E_NULL", 2: "DFR_E_SHAPE", 3: "DFR_E_WCS",
                 4: "DFR_E_UNSUPPORTED", 5: "DFR_E_DEVICE", 6: "DFR_E_NOMEM", 7: "DFR_E_ARG"}
 
 EXPORTED = [
-    "dfr_options_init", "dfr_reproject", "dfr_reproject_batch", "dfr_wcs_grad_size",
+    "dfr_options_init", "dfr_reproject", "dfr_reproject_batch", "dfr_coadd_batch",
+    "dfr_wcs_grad_size",
     "dfr_reproject_backward", "dfr_sq_residual", "dfr_autotune", "dfr_autotune_batch",
     "dfr_tile_count", "dfr_tile_shape", "dfr_cd_from_pc_cdelt", "dfr_check_wcs",
     "dfr_cell_model", "dfr_release", "dfr_strerror", "dfr_abi_version",
@@ -76,6 +77,9 @@ def _load():
     L.dfr_reproject.restype = st
     L.dfr_reproject_batch.argtypes = [i32, C.POINTER(dfr_frame), W, i32, i32, st, vp, vp, O, vp]
     L.dfr_reproject_batch.restype = st
+    L.dfr_coadd_batch.argtypes = [i32, C.POINTER(dfr_frame), W, i32, i32, st, vp, vp, vp, i32,
+                                  O, vp]
+    L.dfr_coadd_batch.restype = st
     L.dfr_wcs_grad_size.argtypes = [W]
     L.dfr_wcs_grad_size.restype = i64
     L.dfr_reproject_backward.argtypes = [vp, i32, i32, i64, W, W, i32, i32, st, vp, vp, vp, O, vp]
@@ -129,6 +133,13 @@ def dfr_reproject_batch(n, frames, tgt_wcs, out_h, out_w, interp, outs, footprin
                         stream) -> int:
     return lib.dfr_reproject_batch(n, frames, C.byref(tgt_wcs), out_h, out_w, interp, outs,
                                    footprints, C.byref(opt) if opt is not None else None, stream)
+
+
+def dfr_coadd_batch(n, frames, tgt_wcs, out_h, out_w, interp, sum_wf, sum_f, coadd, accumulate,
+                    opt, stream) -> int:
+    return lib.dfr_coadd_batch(n, frames, C.byref(tgt_wcs), out_h, out_w, interp, sum_wf, sum_f,
+                               coadd, accumulate, C.byref(opt) if opt is not None else None,
+                               stream)
 
 
 def dfr_wcs_grad_size(src_wcs) -> int:

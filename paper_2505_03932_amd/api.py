@@ -6,6 +6,7 @@ runs in libdfr's HIP kernels.
   reproject(src, src_wcs, tgt_wcs, shape_out, order)       single image
   calculate_reprojection(source_hdus, target_wcs, ...)     the paper's call
   reproject_batch(srcs, src_wcss, tgt_wcs, shape_out)      many frames
+  coadd_batch(srcs, src_wcss, tgt_wcs, shape_out)          footprint-weighted stack
   ReprojectFn / reproject_differentiable(...)              autograd
   sq_residual(out, ref, mask)                              alignment loss
 
@@ -221,6 +222,38 @@ def reproject_batch(srcs: Sequence[torch.Tensor], src_wcss, tgt_wcs, shape_out, 
                                  _stream(dev))
     _check(s, "dfr_reproject_batch")
     return outs, (fps if footprint else None)
+
+
+def coadd_batch(srcs: Sequence[torch.Tensor], src_wcss, tgt_wcs, shape_out, order="bilinear",
+                *, sum_wf=None, sum_f=None, coadd=True, accumulate=False, cubic_a=-0.5,
+                nan_outside=False, tile=0):
+    """Stack many frames onto one target grid, each weighted by its footprint.
+
+    Returns (coadd, sum_wf, sum_f): [H, W] float32 tensors with
+    sum_wf = sum of out_i * F_i and sum_f = sum of F_i over the frames, and
+    coadd = sum_wf / sum_f where sum_f > 0 (None when ``coadd`` is False).
+    With ``accumulate`` the given ``sum_wf`` / ``sum_f`` are added to."""
+    srcs = [_src_tensor(s) for s in srcs]
+    oh, ow = int(shape_out[0]), int(shape_out[1])
+    if accumulate and (sum_wf is None or sum_f is None):
+        raise ValueError("accumulate needs sum_wf and sum_f")
+    dev = srcs[0].device if srcs else (sum_wf.device if sum_wf is not None else torch.device("cuda"))
+    if sum_wf is None:
+        sum_wf = torch.empty((oh, ow), dtype=torch.float32, device=dev)
+    if sum_f is None:
+        sum_f = torch.empty((oh, ow), dtype=torch.float32, device=dev)
+    for t in (sum_wf, sum_f):
+        if t.dtype != torch.float32 or t.shape != (oh, ow) or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("sum_wf and sum_f must be contiguous float32 [H, W] device tensors")
+    img = torch.empty((oh, ow), dtype=torch.float32, device=dev) if coadd else None
+    frames, keep = _frames(srcs, src_wcss) if srcs else (None, [])
+    tw = CWcs(tgt_wcs)
+    o = _opts("f32", cubic_a, nan_outside, tile)
+    s = _lib.dfr_coadd_batch(len(srcs), frames, tw.s, oh, ow, ORDERS[order], sum_wf.data_ptr(),
+                             sum_f.data_ptr(), img.data_ptr() if img is not None else None,
+                             1 if accumulate else 0, o, _stream(dev))
+    _check(s, "dfr_coadd_batch")
+    return img, sum_wf, sum_f
 
 
 def autotune(src, src_wcs, tgt_wcs, shape_out, order="bilinear", cubic_a=-0.5) -> int:

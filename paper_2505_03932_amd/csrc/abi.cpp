@@ -97,9 +97,10 @@ dfr_status prepare_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_
                          int32_t out_h, int32_t out_w, int interp, float *const *outs,
                          float *const *footprints, const dfr_options *opt,
                          std::vector<FramePlan> &plans, TileGeom &G, int &tile, int &np,
-                         int &max_sord) {
+                         int &max_sord, bool stack = false) {
+  // stack: a coadd, whose frames have no outputs of their own (outs unused)
   if (n < 0) return DFR_E_ARG;
-  if (n > 0 && (!frames || !outs)) return DFR_E_NULL;
+  if (n > 0 && (!frames || (!outs && !stack))) return DFR_E_NULL;
   if (!tgt_wcs) return DFR_E_NULL;
   if (out_h < 0 || out_w < 0) return DFR_E_SHAPE;
   if (!interp_ok(interp)) return DFR_E_UNSUPPORTED;
@@ -118,7 +119,7 @@ dfr_status prepare_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_
       if (f.pitch < f.w) return DFR_E_SHAPE;
     }
     if ((s = check_wcs(&f.wcs, true)) != DFR_OK) return s;
-    if ((int64_t)out_h * out_w > 0 && !outs[i]) return DFR_E_NULL;
+    if (!stack && (int64_t)out_h * out_w > 0 && !outs[i]) return DFR_E_NULL;
   }
   plans.clear();
   if (n == 0 || out_h == 0 || out_w == 0) {
@@ -130,18 +131,18 @@ dfr_status prepare_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_
   for (int i = 0; i < n; ++i) {
     const dfr_frame &f = frames[i];
     const float *src = (f.h > 0 && f.w > 0) ? f.src : nullptr;
-    build_plan(src, f.h, f.w, f.pitch, f.wcs, *tgt_wcs, out_h, out_w, outs[i],
-               footprints ? footprints[i] : nullptr, plans[i]);
+    build_plan(src, f.h, f.w, f.pitch, f.wcs, *tgt_wcs, out_h, out_w, stack ? nullptr : outs[i],
+               (footprints && !stack) ? footprints[i] : nullptr, plans[i]);
     max_sord = std::max(max_sord, plans[i].s_order);
   }
   // run-time-order kernel for high orders and whenever the target has SIP
   if (max_sord > 5 || plans[0].t_order > 0) max_sord = 6;
   tile = o.tile;
-  if (tile == 0) {
+  if (tile == 0 && !stack) {
     std::lock_guard<std::mutex> lk(tune_mutex_for_batch());
     tile = tuned_tile(batch_key(plans, out_h, out_w, interp, max_sord));
   }
-  if (tile == 0) tile = kDefaultTile;
+  if (tile == 0) tile = stack ? kCoaddTile : kDefaultTile;
   batch_geom(plans, out_h, out_w, interp, tile, o, G, np);
   return DFR_OK;
 }
@@ -240,6 +241,37 @@ dfr_status dfr_reproject_batch(int32_t n, const dfr_frame *frames, const dfr_wcs
   resolve_options(opt, o);
   return run_batch(plans, G, (int)interp, np, max_sord, o.precision == DFR_PREC_F32,
                    reinterpret_cast<hipStream_t>(stream), true);
+}
+
+dfr_status dfr_coadd_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_wcs,
+                           int32_t out_h, int32_t out_w, dfr_interp interp, float *sum_wf,
+                           float *sum_f, float *coadd, int32_t accumulate,
+                           const dfr_options *opt, void *stream) {
+  std::vector<FramePlan> plans;
+  int tile = 0, np = 0, max_sord = 0;
+  TileGeom G;
+  dfr_status s = prepare_batch(n, frames, tgt_wcs, out_h, out_w, (int)interp, nullptr, nullptr,
+                               opt, plans, G, tile, np, max_sord, true);
+  if (s != DFR_OK) return s;
+  if (out_h == 0 || out_w == 0) return DFR_OK;
+  if (!sum_wf || !sum_f) return DFR_E_NULL;
+  dfr_options o;
+  resolve_options(opt, o);
+  const CoaddOut C{sum_wf, sum_f, coadd, accumulate ? 1 : 0};
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (plans.empty()) {
+    // an empty stack: the sums stay (accumulate) or become 0
+    FramePlan P;
+    build_plan(nullptr, 0, 0, 0, *tgt_wcs, *tgt_wcs, out_h, out_w, nullptr, nullptr, P);
+    TileShape ts;
+    make_geom(P, out_h, out_w, (int)interp, o.tile ? o.tile : kCoaddTile, o, G, ts);
+    G.lds_cap = 0;
+    return launch_coadd_f32(nullptr, 0, 0, G, (int)interp, ts.np, C, st) == hipSuccess
+               ? DFR_OK
+               : DFR_E_DEVICE;
+  }
+  return run_batch(plans, G, (int)interp, np, max_sord, o.precision == DFR_PREC_F32, st, false,
+                   &C);
 }
 
 dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w,

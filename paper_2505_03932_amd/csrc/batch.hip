@@ -1,4 +1,4 @@
-// Launch helpers of the persistent batch kernel (defined in
+// Launch helpers of the persistent batch and the coadd kernels (defined in
 // tile_kernels.hpp).
 #include "tile_kernels.hpp"
 
@@ -10,6 +10,12 @@ const void *batch_kernel_ptr(int interp, int np, int sord) {
   return interp == DFR_NEAREST    ? batch_kernel_for<DFR_NEAREST>(np, sord)
          : interp == DFR_BILINEAR ? batch_kernel_for<DFR_BILINEAR>(np, sord)
                                   : batch_kernel_for<DFR_BICUBIC>(np, sord);
+}
+
+const void *coadd_kernel_ptr(int interp, int np, int sord) {
+  return interp == DFR_NEAREST    ? coadd_kernel_for<DFR_NEAREST>(np, sord)
+         : interp == DFR_BILINEAR ? coadd_kernel_for<DFR_BILINEAR>(np, sord)
+                                  : coadd_kernel_for<DFR_BICUBIC>(np, sord);
 }
 
 int batch_blocks_per_cu(int interp, int np, int sord, int lds_bytes) {
@@ -29,6 +35,16 @@ hipError_t launch_batch_f32(const FramePlan *plans_dev, int n_frames, int max_so
   BatchKernel k = reinterpret_cast<BatchKernel>(const_cast<void *>(batch_kernel_ptr(interp, np, max_sord)));
   size_t lds = (size_t)G.lds_cap * sizeof(float);
   hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, stream, plans_dev, n_frames, G, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_coadd_f32(const FramePlan *plans_dev, int n_frames, int max_sord,
+                            const TileGeom &G, int interp, int np, const CoaddOut &C,
+                            hipStream_t stream) {
+  using CoaddKernel = void (*)(const FramePlan *, int, TileGeom, CoaddOut);
+  CoaddKernel k = reinterpret_cast<CoaddKernel>(const_cast<void *>(coadd_kernel_ptr(interp, np, max_sord)));
+  size_t lds = (size_t)G.lds_cap * sizeof(float);
+  hipLaunchKernelGGL(k, dim3(G.n_tiles), dim3(kThreads), lds, stream, plans_dev, n_frames, G, C);
   return hipGetLastError();
 }
 

@@ -84,6 +84,15 @@ struct TileGeom {
   double *debug;              // [out_h][out_w][2] source positions, or null
 };
 
+// Outputs of the coadd kernel: device [out_h][out_w] float32 each, not
+// overlapping; coadd nullable.
+struct CoaddOut {
+  float *sum_wf;       // sum over frames of out * F
+  float *sum_f;        // sum over frames of F
+  float *coadd;        // sum_wf / sum_f where sum_f > 0
+  int32_t accumulate;  // add to the sums already there instead of starting at 0
+};
+
 // Per-cell quantities from the FP64 anchor evaluation (kept in LDS).
 struct alignas(16) Anchor {
   float g1, g2, f1, f2, k1, k2;  // dU = (g.d)/(1 + k.d), dV = (f.d)/(1 + k.d)
@@ -494,6 +503,16 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
 // the 4 rows x 16 runs of 4 pixels a wave touches at once fall in distinct
 // banks (rows shift the bank by 1, 2, 3 instead of a multiple of 4).
 __host__ __device__ __forceinline__ int lds_pitch(int bw) { return bw + ((1 - bw) & 3); }
+
+// Every image and table pointer the library hands a kernel is in global
+// memory.  The compiler knows that for pointers passed as kernel arguments,
+// not for pointers read from a frame table in memory, whose accesses it then
+// emits as flat accesses (64-bit VGPR addresses, waits on both counters);
+// this restores the address space.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *global_ptr(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
 
 // Work-group index -> tile index, so that the ~n/8 consecutive (spatially
 // adjacent) tiles land on the same XCD: work-groups are dealt round-robin

@@ -260,9 +260,9 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
 __device__ __forceinline__ void stage_box(const FramePlan &P, int bi0, int bj0, int bw, int bh,
                                           int lp, float *__restrict__ lds) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const float *__restrict__ s0 = P.src + (int64_t)bj0 * P.pitch + bi0;
+  const auto *__restrict__ s0 = global_ptr(P.src) + (int64_t)bj0 * P.pitch + bi0;
   for (int r = wave; r < bh; r += kThreads / 64) {
-    const float *__restrict__ sr = s0 + (int64_t)r * P.pitch;
+    const auto *__restrict__ sr = s0 + (int64_t)r * P.pitch;
     float *__restrict__ lr = lds + r * lp;
     for (int col = lane; col < bw; col += 64) lr[col] = sr[col];
   }
@@ -274,12 +274,14 @@ __device__ __forceinline__ void stage_box(const FramePlan &P, int bi0, int bj0, 
 __device__ __forceinline__ void store_run(float *__restrict__ base, int64_t off, int x, int out_w,
                                           bool vec, const float v[kRun]) {
   typedef float f4v __attribute__((ext_vector_type(4)));
+  auto *g = global_ptr(base) + off;
   if (vec && x + kRun <= out_w) {
-    __builtin_nontemporal_store((f4v){v[0], v[1], v[2], v[3]}, reinterpret_cast<f4v *>(base + off));
+    __builtin_nontemporal_store((f4v){v[0], v[1], v[2], v[3]},
+                                (__attribute__((address_space(1))) f4v *)g);
   } else {
 #pragma unroll
     for (int e = 0; e < kRun; ++e)
-      if (x + e < out_w) __builtin_nontemporal_store(v[e], base + off + e);
+      if (x + e < out_w) __builtin_nontemporal_store(v[e], g + e);
   }
 }
 
@@ -307,7 +309,7 @@ __device__ __forceinline__ bool nearest_exact(const FramePlan &P, int x, int y, 
 // ------------------------------------------------ shared by the forward --
 //
 // Interpolation, store and position helpers of the forward kernels
-// (forward_cells.hpp): the interior formulas below are the ones every path
+// (forward_tile.hpp): the interior formulas below are the ones every path
 // uses, so results agree bit for bit wherever all taps are inside.
 
 // Values of one pixel's in-image taps combined the same way on every path

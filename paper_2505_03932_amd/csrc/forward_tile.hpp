@@ -17,7 +17,8 @@
 //      others take the general path (zero padding, footprint normalisation,
 //      global fetches for taps outside the box).
 // Positions depend only on the pixel's cell (its model or anchor), never on
-// the tile shape, so every tile shape and the batch give identical results.
+// the tile shape, so every tile shape, the batch and the coadd give identical
+// per-pixel results.  A sink takes them (stores, or the coadd's sums).
 #pragma once
 
 #include "forward_body.hpp"
@@ -45,10 +46,10 @@ struct FwdShared {
 __device__ __forceinline__ void dma_box(const FramePlan &P, int bi0, int bj0, int bw, int bh,
                                         int lp, float *__restrict__ lds) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const float *__restrict__ s0 = P.src + (int64_t)bj0 * P.pitch + bi0;
+  const auto *__restrict__ s0 = global_ptr(P.src) + (int64_t)bj0 * P.pitch + bi0;
 #pragma unroll 1
   for (int r = wave; r < bh; r += kThreads / 64) {
-    const float *sr = s0 + (int64_t)r * P.pitch;
+    const auto *sr = s0 + (int64_t)r * P.pitch;
 #pragma unroll 1
     for (int c0 = 0; c0 < bw; c0 += 64) {
       if (c0 + lane < bw)
@@ -103,11 +104,51 @@ __device__ __forceinline__ bool tile_out_of_reach(const FramePlan &P, const Tile
   return cx1 < kReachBig - r0 || cx0 >= r1 || cy1 < kReachBig - r2 || cy0 >= r3;
 }
 
+// Where the results of a forward tile go.  StoreSink writes each pixel's
+// value and footprint to the frame's outputs (dfr_reproject, the batch);
+// StackSink adds out * F and F of every covered pixel to per-thread
+// accumulators (the coadd), so the per-pixel arithmetic is the same code
+// either way.
+struct StoreSink {
+  template <int NP>
+  __device__ __forceinline__ void uncovered(const FramePlan &P, const TileGeom &G, int tile) {
+    tile_uncovered<NP>(P, G, tile);
+  }
+  // row k of the thread's runs; `full`: every footprint is exactly 1
+  __device__ __forceinline__ void row(const FramePlan &P, const TileGeom &G, int k, int64_t off,
+                                      int xr, bool vec, bool full, const float o[kRun],
+                                      const float f[kRun]) {
+    store_run(P.out, off, xr, G.out_w, vec, o);
+    if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, f);
+  }
+};
+
+template <int NP>
+struct StackSink {
+  float s[NP][kRun];  // sum of out * F
+  float w[NP][kRun];  // sum of F
+  template <int NP_>
+  __device__ __forceinline__ void uncovered(const FramePlan &, const TileGeom &, int) {}
+  __device__ __forceinline__ void row(const FramePlan &, const TileGeom &, int k, int64_t, int,
+                                      bool, bool full, const float o[kRun], const float f[kRun]) {
+#pragma unroll
+    for (int e = 0; e < kRun; ++e) {
+      if (full) {
+        s[k][e] += o[e];  // F = 1: out * F is out exactly
+        w[k][e] += 1.0f;
+      } else if (f[e] > 0.0f) {
+        s[k][e] = fmaf(o[e], f[e], s[k][e]);
+        w[k][e] += f[e];
+      }
+    }
+  }
+};
+
 // The target SIP is compiled only into the run-time-order variant (the
 // launcher uses it whenever the target WCS has A/B).
-template <int INTERP, int SORD, int NP>
+template <int INTERP, int SORD, int NP, class Sink>
 __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom &G, int tile,
-                                             float *__restrict__ lds, FwdShared &sh) {
+                                             float *__restrict__ lds, FwdShared &sh, Sink &sink) {
   constexpr bool TSIP = SORD == kRtOrder;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int lg = G.txt_log2;
@@ -134,10 +175,11 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
           // the model covers every pixel of the cell: the box needs only the
           // tap support (+1 px kept as a guard)
           constexpr int lo = TapSupport<INTERP>::lo + 1, hi = TapSupport<INTERP>::hi + 1;
+          typedef unsigned u4v __attribute__((ext_vector_type(4)));
 #pragma unroll
           for (int part = 0; part < (int)(sizeof(CellModel) / 16); ++part)
-            reinterpret_cast<uint4 *>(&sh.cell[tid].model)[part] =
-                reinterpret_cast<const uint4 *>(Mg)[part];
+            reinterpret_cast<u4v *>(&sh.cell[tid].model)[part] =
+                global_ptr(reinterpret_cast<const u4v *>(Mg))[part];
           const CellModel &M = sh.cell[tid].model;
           // the part of the cell inside the tile and the output, as offsets
           // from the cell centre; extremes of the linear part there, grown
@@ -212,7 +254,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   const bool vec = vector_stores_ok(P, G);
   const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
   if (!sh.touch && G.allow_skip) {
-    tile_uncovered<NP>(P, G, tile);
+    sink.template uncovered<NP>(P, G, tile);
     return;
   }
 
@@ -344,16 +386,14 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
         }
         f[e] = 1.0f;
       }
-      const int64_t off = (int64_t)y * G.out_w + xr;
-      store_run(P.out, off, xr, G.out_w, vec, o);
-      if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, f);
+      sink.row(P, G, k, (int64_t)y * G.out_w + xr, xr, vec, true, o, f);
     }
     return;
   }
   // general path: source coordinates, zero padding, footprint normalisation;
   // taps come from LDS when the pixel's in-image taps are inside the box
   auto fl = [&](int i, int j) -> float { return lds[__umul24(j - bj0, lp) + (i - bi0)]; };
-  auto fg = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
+  auto fg = [&](int i, int j) -> float { return global_ptr(P.src)[(int64_t)j * P.pitch + i]; };
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     const int y = y0 + ty + k * RP;
@@ -381,9 +421,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
         }
       }
     }
-    const int64_t off = (int64_t)y * G.out_w + xr;
-    store_run(P.out, off, xr, G.out_w, vec, o);
-    if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, f);
+    sink.row(P, G, k, (int64_t)y * G.out_w + xr, xr, vec, false, o, f);
   }
 }
 

@@ -11,6 +11,7 @@ namespace dfr {
 // 8 << li (tile width 32 << li px) and NP = 1 << ni rows per thread.
 constexpr int kTileCount = 12;
 constexpr int kDefaultTile = 5;  // 64 x 32
+constexpr int kCoaddTile = 5;    // coadd default
 
 struct TileShape {
   int txt_log2;  // threads per tile row, log2
@@ -51,6 +52,10 @@ hipError_t launch_batch_f32(const FramePlan *plans_dev, int n_frames, int max_so
                             const TileGeom &G, int interp, int np, int *counter,
                             int grid, hipStream_t stream);
 const void *batch_kernel_ptr(int interp, int np, int sord);
+// Coadd of a frame table: one work-group per target tile (G.n_tiles).
+hipError_t launch_coadd_f32(const FramePlan *plans_dev, int n_frames, int max_sord,
+                            const TileGeom &G, int interp, int np, const CoaddOut &C,
+                            hipStream_t stream);
 const void *zero_i32_kernel_ptr();
 int batch_blocks_per_cu(int interp, int np, int sord, int lds_bytes);
 // Number of per-tile FP64 partial sums the backward kernel produces for a

@@ -221,7 +221,9 @@ void release_workspaces() {
 // ----------------------------------------------------------------- batch --
 
 dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int interp, int np,
-                     int max_sord, bool models, hipStream_t stream, bool graph) {
+                     int max_sord, bool models, hipStream_t stream, bool graph,
+                     const CoaddOut *coadd) {
+  if (coadd) graph = false;  // its output pointers are kernel arguments
   std::lock_guard<std::mutex> lk(g_ws_mutex);
   Workspace *w = workspace(stream);
   if (!w) return DFR_E_DEVICE;
@@ -282,9 +284,10 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
     if (models && hipLaunchKernel(cell_models_batch_ptr(max_sord), mgrid, dim3(64), margs, 0,
                                   stream) != hipSuccess)
       return DFR_E_DEVICE;
-    if (launch_batch_f32(plans_dev, n, max_sord, G, interp, np, counter, grid, stream) !=
-        hipSuccess)
-      return DFR_E_DEVICE;
+    const hipError_t e =
+        coadd ? launch_coadd_f32(plans_dev, n, max_sord, G, interp, np, *coadd, stream)
+              : launch_batch_f32(plans_dev, n, max_sord, G, interp, np, counter, grid, stream);
+    if (e != hipSuccess) return DFR_E_DEVICE;
   } else {
     BatchGraph *found = nullptr;
     for (auto &g : w->graphs)

@@ -64,8 +64,10 @@ void release_workspaces();
 
 // Reproject a batch in one persistent launch; `graph` replays a cached HIP
 // graph (frame-table copy, per-cell models of every frame when `models`,
-// counter reset, persistent kernel).
+// counter reset, persistent kernel).  With `coadd` the frames are stacked
+// into its sums instead (eager launches, one work-group per target tile).
 dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int interp, int np,
-                     int max_sord, bool models, hipStream_t stream, bool graph);
+                     int max_sord, bool models, hipStream_t stream, bool graph,
+                     const CoaddOut *coadd = nullptr);
 
 }  // namespace dfr

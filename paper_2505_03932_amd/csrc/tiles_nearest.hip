@@ -1,7 +1,8 @@
-// Tiled forward and batch kernels, nearest interpolation.
+// Tiled forward, batch and coadd kernels, nearest interpolation.
 #include "tile_kernels.hpp"
 
 namespace dfr {
 template const void *tile_kernel_for<DFR_NEAREST>(int, int);
 template const void *batch_kernel_for<DFR_NEAREST>(int, int);
+template const void *coadd_kernel_for<DFR_NEAREST>(int, int);
 }  // namespace dfr

@@ -145,6 +145,18 @@ def test_batch_backward_loss_errors(L):
     L.dfr_options_init(o)
     o.precision = 1
     assert L.dfr_reproject_batch(1, frames, T.s, 4, 4, 1, outs, None, o, None) == 4
+    # coadd: the same frame checks, both sums required, FP32 only
+    frames[0].pitch = 4
+    assert L.dfr_coadd_batch(1, frames, T.s, 4, 4, 1, 1, 1, None, 0, None, None) == 2
+    frames[0].pitch = 8
+    assert L.dfr_coadd_batch(-1, frames, T.s, 4, 4, 1, 1, 1, None, 0, None, None) == 7
+    assert L.dfr_coadd_batch(1, None, T.s, 4, 4, 1, 1, 1, None, 0, None, None) == 1
+    assert L.dfr_coadd_batch(1, frames, T.s, 4, 4, 3, 1, 1, None, 0, None, None) == 4
+    assert L.dfr_coadd_batch(1, frames, T.s, 4, 4, 1, None, 1, None, 0, None, None) == 1
+    assert L.dfr_coadd_batch(1, frames, T.s, 4, 4, 1, 1, None, 1, 0, None, None) == 1
+    assert L.dfr_coadd_batch(1, frames, T.s, 4, 4, 1, 1, 1, None, 0, o, None) == 4
+    assert L.dfr_coadd_batch(1, frames, T.s, -4, 4, 1, 1, 1, None, 0, None, None) == 2
+    assert L.dfr_coadd_batch(1, frames, T.s, 0, 4, 1, None, None, None, 0, None, None) == 0
     # backward: FP32 only, inverse SIP order <= 5, gradient input required
     assert L.dfr_reproject_backward(1, 8, 8, 8, S.s, T.s, 4, 4, 1, None, None, None, None,
                                     None) == 1

@@ -528,3 +528,82 @@ def test_parameter_gradient_vs_central_differences(orc, interp):
         # after the sky stage, where the rounding is ~1e-12 px.
         rel = 2e-5 if name == "crval" else 5e-6
         assert abs(gp[i] - fd) <= rel * abs(fd), (name, k, gp[i], fd)
+
+
+# ----------------------------------------------------------------- coadd --
+# The stack is defined from the per-frame result (out_i, F_i); these pins tie
+# the oracle's sums to closed forms where the footprints are known exactly.
+
+
+def _half_pixel_pair():
+    """Target = frame B's grid; frame A has the same WCS with CRPIX1 + 0.5,
+    so A's column of target column x is x + 0.5 and A (30 columns wide)
+    covers x <= 28 fully, x = 29 with footprint 1/2 (bilinear) and nothing
+    beyond."""
+    wb = WcsParams.tan((150.0, 2.0), 2.85, 0.0, (40, 60))
+    wa = wb.copy(crpix=(wb.crpix[0] + 0.5, wb.crpix[1]))
+    return wa, wb
+
+
+def test_coadd_half_pixel_edge_closed_form(orc):
+    wa, wb = _half_pixel_pair()
+    ca, cb = 3.0, 11.0
+    sa = np.full((40, 30), ca, np.float32)
+    sb = np.full((40, 60), cb, np.float32)
+    img, swf, sf = orc.coadd([sa, sb], [wa, wb], wb, (40, 60), "bilinear")
+    assert np.allclose(sf[:, :29], 2.0, atol=1e-8) and np.allclose(img[:, :29], (ca + cb) / 2, atol=1e-8)
+    assert np.allclose(sf[:, 29], 1.5, atol=1e-8)
+    assert np.allclose(img[:, 29], (0.5 * ca + cb) / 1.5, atol=1e-8)
+    assert np.allclose(swf[:, 29], 0.5 * ca + cb, atol=1e-7)
+    assert np.allclose(sf[:, 30:], 1.0, atol=1e-8) and np.allclose(img[:, 30:], cb, atol=1e-8)
+
+
+@pytest.mark.parametrize("interp", ["nearest", "bilinear", "bicubic"])
+def test_coadd_of_constant_frames_is_constant(orc, interp):
+    """Footprint normalisation reproduces a constant frame wherever it
+    covers, so a stack of frames of one constant is that constant wherever
+    any frame covers, whatever the frames' geometry."""
+    tw = WcsParams.tan((150.0, 2.0), 2.85, 0.0, (90, 100))
+    rng = np.random.default_rng(5)
+    srcs, wcss = [], []
+    for k in range(4):
+        h, w = int(rng.integers(20, 70)), int(rng.integers(20, 70))
+        wcss.append(WcsParams.tan((150.0 + rng.uniform(-0.01, 0.01), 2.0 + rng.uniform(-0.01, 0.01)),
+                                  rng.uniform(2.0, 3.5), rng.uniform(-30, 30), (h, w)))
+        srcs.append(np.full((h, w), 7.25, np.float32))
+    img, swf, sf = orc.coadd(srcs, wcss, tw, (90, 100), interp)
+    cov = sf > 0
+    assert cov.sum() > 2000 and (~cov).sum() > 100
+    assert np.allclose(img[cov], 7.25, rtol=1e-12, atol=0)
+    assert np.all(img[~cov] == 0) and np.all(swf[~cov] == 0)
+
+
+def test_coadd_of_copies_and_invariances(orc):
+    c = configs.plain()
+    out, fp = orc.reproject(c.src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic")
+    img, swf, sf = orc.coadd([c.src] * 3, [c.src_wcs] * 3, c.tgt_wcs, c.out_shape, "bicubic")
+    cov = fp > 0
+    assert np.array_equal(sf > 0, cov)
+    assert np.allclose(sf[cov], 3 * fp[cov], rtol=1e-14)
+    assert np.allclose(img[cov], out[cov], rtol=1e-12, atol=1e-9)
+    # frame order and a common scale of the sources
+    w2 = c.src_wcs.copy(crval=(c.src_wcs.crval[0] + 2e-4, c.src_wcs.crval[1] - 1e-4))
+    s2 = (c.src * 0.5 + 3.0).astype(np.float32)
+    a = orc.coadd([c.src, s2], [c.src_wcs, w2], c.tgt_wcs, c.out_shape, "bilinear")
+    b = orc.coadd([s2, c.src], [w2, c.src_wcs], c.tgt_wcs, c.out_shape, "bilinear")
+    assert np.allclose(a[0], b[0], rtol=1e-13, atol=1e-10)
+    k = orc.coadd([c.src * np.float32(4), s2 * np.float32(4)], [c.src_wcs, w2], c.tgt_wcs,
+                  c.out_shape, "bilinear")
+    assert np.allclose(k[0], 4 * a[0], rtol=1e-12, atol=1e-9)
+    assert np.array_equal(k[2], a[2])
+
+
+def test_coadd_rows_and_empty_stack(orc):
+    c = configs.plain()
+    rows = np.array([0, 17, 200, 255], dtype=np.int64)
+    full = orc.coadd([c.src], [c.src_wcs], c.tgt_wcs, c.out_shape, "bilinear")
+    part = orc.coadd([c.src], [c.src_wcs], c.tgt_wcs, c.out_shape, "bilinear", rows=rows)
+    for f, p in zip(full, part):
+        assert np.array_equal(f[rows], p)
+    img, swf, sf = orc.coadd([], [], c.tgt_wcs, (5, 7), nan_outside=True)
+    assert np.all(np.isnan(img)) and not swf.any() and not sf.any()
