@@ -14,10 +14,15 @@ step is the two launches, so this bounds the tile kernel's own fraction from
 below), the HBM traffic the committed rocprofv3 PMC summary measured,
 the FP64 CPU oracle timed on this host, and the other forms of the path
 (nearest and bicubic, the FP64 and trigonometric forms, forward+backward on
-the 2048^2 alignment case, the 64-frame batch, the +89.5 deg precision case).
+the 2048^2 alignment case, the 64-frame batch and its coadd, the +89.5 deg
+precision case).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras]
-                    [--no-cpu-baseline] [--calibrate-copy]
+                    [--no-cpu-baseline] [--calibrate-copy] [--sweep]
+
+--sweep prints, instead, one JSON line with the size sweep of the paper's
+scaling benchmark: 256^2 .. 4000x6000 x {nearest, bilinear, bicubic} x
+{with, without SIP}.
 
 --calibrate-copy adds, after the timed steps, three plain device copies of a
 512,000,000-byte buffer, each from a source pushed out of the caches by a
@@ -267,6 +272,32 @@ def extra_pole(dfr, steps):
     return res
 
 
+SWEEP_SIZES = [(256, 256), (512, 512), (1024, 1024), (2048, 2048), (4000, 6000)]
+
+
+def sweep(dfr, steps, warmup):
+    """The paper's scaling benchmark (section 4): image sizes 256^2 to
+    4000x6000, each interpolation, with and without SIP; per point the whole
+    forward step (cell models + tiles) on device-resident buffers."""
+    import torch
+    from synth import configs
+    rows = []
+    for shape in SWEEP_SIZES:
+        for sip in (False, True):
+            c = configs.sweep(shape, sip=sip)
+            for interp in ("nearest", "bilinear", "bicubic"):
+                fr = Frame(dfr, c.src, c.src_wcs, c.tgt_wcs, c.out_shape, interp)
+                ms, _ = time_steps(fr.step, steps, warmup)
+                npx = shape[0] * shape[1]
+                rows.append({"h": shape[0], "w": shape[1], "sip": sip, "interp": interp,
+                             "us": round(ms * 1e3, 2), "mpix_s": round(npx / ms / 1e3, 1),
+                             "hbm_frac_12Bpx": round(12 * npx / ms / 1e6 / HBM_PEAK_GBS, 4)})
+                log(json.dumps(rows[-1]))
+                del fr
+            torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,6 +306,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="print the size x interpolation x SIP sweep instead of the headline")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs the reprojection on a single MI355X "
@@ -284,6 +317,15 @@ def main():
     import torch
     import paper_2505_03932_amd as dfr
     from synth import configs
+
+    if args.sweep:
+        rows = sweep(dfr, args.steps, args.warmup)
+        print(json.dumps({"metric": "output Mpix/s per size, interpolation and SIP",
+                          "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": "size sweep 256^2 .. 4000x6000"},
+                          "sweep": rows}), flush=True)
+        return
 
     t0 = time.perf_counter()
     case = configs.sip3(interp=1)

@@ -87,6 +87,26 @@ def sip3(seed: int = 2, scale: float = 1.0, interp: int = BILINEAR,
     return Case("sip3", src, sw, tw, (h, w), interp, extra={"inverse_fit_resid_px": resid})
 
 
+def sweep(shape_hw, sip: bool = True, seed: int = 8, interp: int = BILINEAR) -> Case:
+    """One point of the size sweep: an (h, w) frame with the 6000x4000 frame's
+    recipe (star density, sky, 2.85"/px at (150, +2)); with ``sip`` a SIP
+    order-3 distortion scaled to the frame and its fitted order-4 inverse.
+    The target is the same size, its CRVAL 40 px along +x and rotated 0.3 deg."""
+    rng = np.random.default_rng(seed)
+    h, w = shape_hw
+    n_stars = max(1, int(round(STAR_DENSITY_PER_MPIX * h * w / 1e6)))
+    src = star_field(h, w, 300.0, 10.0, n_stars, seed, rng=rng)
+    sw = WcsParams.tan((150.0, 2.0), 2.85, 0.0, (h, w))
+    if sip:
+        a, b = draw_sip(3, 0.5 * max(h, w), rng)
+        ap, bp, _ = fit_inverse_sip(a, b, 4, sw.crpix, (h, w))
+        sw = sw.copy(a=a, b=b, ap=ap, bp=bp)
+    s_deg = 2.85 / 3600.0
+    ra_t = 150.0 - 40.0 * s_deg / math.cos(math.radians(2.0))
+    tw = WcsParams.tan((ra_t, 2.0), 2.85, 0.3, (h, w))
+    return Case("sweep", src, sw, tw, (h, w), interp)
+
+
 def batch(seed: int = 3, n_frames: int = 64, target_side: int = 8192,
           side_range=(2048, 6000), interp: int = BILINEAR, images: bool = True) -> Case:
     """64 uneven sub-exposures onto one target.  Frame parameters come from
