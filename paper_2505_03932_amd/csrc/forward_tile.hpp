@@ -144,153 +144,210 @@ struct StackSink {
   }
 };
 
+// Placement of a tile in the output and of this thread's runs in the tile.
+struct TileXY {
+  int TW, RP, TH;   // tile width and height; rows between a thread's runs
+  int x0, y0;       // first output pixel of the tile
+  int cx0, cy0;     // first cell of the tile
+  int ncx, nA;      // cells per tile row, cells of the tile
+  int ty, xr;       // this thread's first row (in the tile) and first column
+};
+
+template <int NP>
+__device__ __forceinline__ TileXY tile_xy(const TileGeom &G, int tile) {
+  TileXY T;
+  const int lg = G.txt_log2;
+  T.TW = kRun << lg;
+  T.RP = kThreads >> lg;
+  T.TH = T.RP * NP;
+  const int trow = tile / G.tiles_x;
+  T.x0 = (tile - trow * G.tiles_x) * T.TW;
+  T.y0 = trow * T.TH;
+  T.cx0 = T.x0 / kCell;
+  T.ncx = T.TW / kCell;
+  T.cy0 = T.y0 / kCell;
+  T.nA = T.ncx * (T.TH >= kCell ? T.TH / kCell : 1);
+  T.ty = threadIdx.x >> lg;
+  T.xr = T.x0 + (threadIdx.x & ((1 << lg) - 1)) * kRun;
+  return T;
+}
+
+// Index of cell i of the tile in the frame's model table.
+__device__ __forceinline__ int64_t tile_cell_index(const TileGeom &G, const TileXY &T, int i) {
+  const int cy = T.cy0 + i / T.ncx, cx = T.cx0 + i % T.ncx;
+  return (int64_t)cy * ((G.out_w + kCell - 1) >> kCellLog2) + cx;
+}
+
+// Phase 1, run by wave 0: per cell of the tile its certified model from the
+// model table, else its FP64 anchor; from them the rigorous source box and
+// the tile's flags, into sh.
 // The target SIP is compiled only into the run-time-order variant (the
 // launcher uses it whenever the target WCS has A/B).
-template <int INTERP, int SORD, int NP, class Sink>
-__device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom &G, int tile,
-                                             float *__restrict__ lds, FwdShared &sh, Sink &sink) {
+template <int INTERP, int SORD, int NP>
+__device__ __forceinline__ void tile_cells(const FramePlan &P, const TileGeom &G, const TileXY &T,
+                                           FwdShared &sh) {
   constexpr bool TSIP = SORD == kRtOrder;
-  const int tid = threadIdx.x, wave = tid >> 6;
-  const int lg = G.txt_log2;
-  const int TW = kRun << lg, RP = kThreads >> lg, TH = RP * NP;
-  const int trow = tile / G.tiles_x;
-  const int x0 = (tile - trow * G.tiles_x) * TW, y0 = trow * TH;
-  const int cx0 = x0 / kCell, ncx = TW / kCell, cy0 = y0 / kCell;
-  const int nA = ncx * (TH >= kCell ? TH / kCell : 1);
-  const int ty = tid >> lg, xr = x0 + (tid & ((1 << lg) - 1)) * kRun;
+  const int tid = threadIdx.x;
   const int W = P.src_w, Hs = P.src_h;
-
-  // ---- 1. per cell: its certified model from the model table, else its
-  // FP64 anchor; from them the source box
-  if (wave == 0) {
-    int t = 0, okc = 1, kind = 0;
-    int imn = 0x3fffffff, imx = -0x3fffffff, jmn = 0x3fffffff, jmx = -0x3fffffff;
-    if (tid < nA) {
-      const int cy = cy0 + tid / ncx, cx = cx0 + tid % ncx;
-      const int xa = cx * kCell, ya = cy * kCell;
-      if (P.models) {
-        const CellModel *Mg = P.models + (cy * ((G.out_w + kCell - 1) >> kCellLog2) + cx);
-        kind = Mg->certified;
-        if (kind) {
-          // the model covers every pixel of the cell: the box needs only the
-          // tap support (+1 px kept as a guard)
-          constexpr int lo = TapSupport<INTERP>::lo + 1, hi = TapSupport<INTERP>::hi + 1;
-          typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  int t = 0, okc = 1, kind = 0;
+  int imn = 0x3fffffff, imx = -0x3fffffff, jmn = 0x3fffffff, jmx = -0x3fffffff;
+  if (tid < T.nA) {
+    const int cy = T.cy0 + tid / T.ncx, cx = T.cx0 + tid % T.ncx;
+    const int xa = cx * kCell, ya = cy * kCell;
+    if (xa >= G.out_w || ya >= G.out_h) {
+      // a cell of a ragged edge tile wholly outside the output: none of its
+      // pixels is computed, it has no model-table entry and adds nothing to
+      // the box (its sh.cell slot is never read for a valid pixel)
+      kind = 1;
+    } else if (P.models) {
+      const CellModel *Mg = P.models + tile_cell_index(G, T, tid);
+      typedef unsigned u4v __attribute__((ext_vector_type(4)));
 #pragma unroll
-          for (int part = 0; part < (int)(sizeof(CellModel) / 16); ++part)
-            reinterpret_cast<u4v *>(&sh.cell[tid].model)[part] =
-                global_ptr(reinterpret_cast<const u4v *>(Mg))[part];
-          const CellModel &M = sh.cell[tid].model;
-          // the part of the cell inside the tile and the output, as offsets
-          // from the cell centre; extremes of the linear part there, grown
-          // by the bound on the rest
-          const float h = (float)kHalfCell;
-          const float a0 = (float)(max(xa, x0) - xa) - h;
-          const float a1 = (float)(min(xa + kCell, min(x0 + TW, G.out_w)) - 1 - xa) - h;
-          const float b0 = (float)(max(ya, y0) - ya) - h;
-          const float b1 = (float)(min(ya + kCell, min(y0 + TH, G.out_h)) - 1 - ya) - h;
-          const float xl = M.mx[0] + fminf(M.mx[4] * a0, M.mx[4] * a1) + fminf(M.mx[1] * b0, M.mx[1] * b1) - M.ex;
-          const float xh = M.mx[0] + fmaxf(M.mx[4] * a0, M.mx[4] * a1) + fmaxf(M.mx[1] * b0, M.mx[1] * b1) + M.ex;
-          const float yl = M.my[0] + fminf(M.my[4] * a0, M.my[4] * a1) + fminf(M.my[1] * b0, M.my[1] * b1) - M.ey;
-          const float yh = M.my[0] + fmaxf(M.my[4] * a0, M.my[4] * a1) + fmaxf(M.my[1] * b0, M.my[1] * b1) + M.ey;
-          imn = M.bx + (int)floorf(xl) - lo;
-          imx = M.bx + (int)floorf(xh) + hi;
-          jmn = M.by + (int)floorf(yl) - lo;
-          jmx = M.by + (int)floorf(yh) + hi;
-          t = (imx >= 0 && imn <= W - 1 && jmx >= 0 && jmn <= Hs - 1) ? 1 : 0;
-        }
-      }
-      if (!kind) {
-        constexpr int lo = TapSupport<INTERP>::lo + 2, hi = TapSupport<INTERP>::hi + 2;
-        Anchor &A = sh.cell[tid].anchor;
-        compute_anchor<SORD, TSIP>(P, xa, ya, TapSupport<INTERP>::hi, A);
-        t = A.touch;
-        okc = A.ok;
+      for (int part = 0; part < (int)(sizeof(CellModel) / 16); ++part)
+        reinterpret_cast<u4v *>(&sh.cell[tid].model)[part] =
+            global_ptr(reinterpret_cast<const u4v *>(Mg))[part];
+      kind = sh.cell[tid].model.certified;
+      if (kind) {
+        // the model covers every pixel of the cell: the box needs only the
+        // tap support (+1 px kept as a guard)
+        constexpr int lo = TapSupport<INTERP>::lo + 1, hi = TapSupport<INTERP>::hi + 1;
+        const CellModel &M = sh.cell[tid].model;
         // the part of the cell inside the tile and the output, as offsets
-        const float ux = (float)(min(xa + kCell, min(x0 + TW, G.out_w)) - 1 - xa);
-        const float vy0 = (float)(max(ya, y0) - ya);
-        const float vy1 = (float)(min(ya + kCell, min(y0 + TH, G.out_h)) - 1 - ya);
-        // extremes of the linear model over that rectangle, grown by the
-        // rigorous bound on the model's error, relative to (bx, by)
-        const float mx = A.ex, my = A.ey;
-        const float x_a = A.sx0 + fminf(0.0f, A.jx[0] * ux) + fminf(A.jx[1] * vy0, A.jx[1] * vy1) - mx;
-        const float x_b = A.sx0 + fmaxf(0.0f, A.jx[0] * ux) + fmaxf(A.jx[1] * vy0, A.jx[1] * vy1) + mx;
-        const float y_a = A.sy0 + fminf(0.0f, A.jy[0] * ux) + fminf(A.jy[1] * vy0, A.jy[1] * vy1) - my;
-        const float y_b = A.sy0 + fmaxf(0.0f, A.jy[0] * ux) + fmaxf(A.jy[1] * vy0, A.jy[1] * vy1) + my;
-        if (okc && fabsf(x_a) < 1.0e7f && fabsf(x_b) < 1.0e7f && fabsf(y_a) < 1.0e7f &&
-            fabsf(y_b) < 1.0e7f) {
-          imn = A.bx + (int)floorf(x_a) - lo;
-          imx = A.bx + (int)floorf(x_b) + hi;
-          jmn = A.by + (int)floorf(y_a) - lo;
-          jmx = A.by + (int)floorf(y_b) + hi;
-        } else {
-          okc = 0;
-        }
+        // from the cell centre; extremes of the linear part there, grown
+        // by the bound on the rest
+        const float h = (float)kHalfCell;
+        const float a0 = (float)(max(xa, T.x0) - xa) - h;
+        const float a1 = (float)(min(xa + kCell, min(T.x0 + T.TW, G.out_w)) - 1 - xa) - h;
+        const float b0 = (float)(max(ya, T.y0) - ya) - h;
+        const float b1 = (float)(min(ya + kCell, min(T.y0 + T.TH, G.out_h)) - 1 - ya) - h;
+        const float xl = M.mx[0] + fminf(M.mx[4] * a0, M.mx[4] * a1) + fminf(M.mx[1] * b0, M.mx[1] * b1) - M.ex;
+        const float xh = M.mx[0] + fmaxf(M.mx[4] * a0, M.mx[4] * a1) + fmaxf(M.mx[1] * b0, M.mx[1] * b1) + M.ex;
+        const float yl = M.my[0] + fminf(M.my[4] * a0, M.my[4] * a1) + fminf(M.my[1] * b0, M.my[1] * b1) - M.ey;
+        const float yh = M.my[0] + fmaxf(M.my[4] * a0, M.my[4] * a1) + fmaxf(M.my[1] * b0, M.my[1] * b1) + M.ey;
+        imn = M.bx + (int)floorf(xl) - lo;
+        imx = M.bx + (int)floorf(xh) + hi;
+        jmn = M.by + (int)floorf(yl) - lo;
+        jmx = M.by + (int)floorf(yh) + hi;
+        t = (imx >= 0 && imn <= W - 1 && jmx >= 0 && jmn <= Hs - 1) ? 1 : 0;
       }
-      sh.kind[tid] = kind;
     }
+    if (!kind) {
+      // no certified model: the cell's FP64 anchor and linear-model bound
+      constexpr int lo = TapSupport<INTERP>::lo + 2, hi = TapSupport<INTERP>::hi + 2;
+      Anchor &A = sh.cell[tid].anchor;
+      compute_anchor<SORD, TSIP>(P, xa, ya, TapSupport<INTERP>::hi, A);
+      t = A.touch;
+      okc = A.ok;
+      // the part of the cell inside the tile and the output, as offsets
+      const float ux = (float)(min(xa + kCell, min(T.x0 + T.TW, G.out_w)) - 1 - xa);
+      const float vy0 = (float)(max(ya, T.y0) - ya);
+      const float vy1 = (float)(min(ya + kCell, min(T.y0 + T.TH, G.out_h)) - 1 - ya);
+      // extremes of the linear model over that rectangle, grown by the
+      // rigorous bound on the model's error, relative to (bx, by)
+      const float mx = A.ex, my = A.ey;
+      const float x_a = A.sx0 + fminf(0.0f, A.jx[0] * ux) + fminf(A.jx[1] * vy0, A.jx[1] * vy1) - mx;
+      const float x_b = A.sx0 + fmaxf(0.0f, A.jx[0] * ux) + fmaxf(A.jx[1] * vy0, A.jx[1] * vy1) + mx;
+      const float y_a = A.sy0 + fminf(0.0f, A.jy[0] * ux) + fminf(A.jy[1] * vy0, A.jy[1] * vy1) - my;
+      const float y_b = A.sy0 + fmaxf(0.0f, A.jy[0] * ux) + fmaxf(A.jy[1] * vy0, A.jy[1] * vy1) + my;
+      if (okc && fabsf(x_a) < 1.0e7f && fabsf(x_b) < 1.0e7f && fabsf(y_a) < 1.0e7f &&
+          fabsf(y_b) < 1.0e7f) {
+        imn = A.bx + (int)floorf(x_a) - lo;
+        imx = A.bx + (int)floorf(x_b) + hi;
+        jmn = A.by + (int)floorf(y_a) - lo;
+        jmx = A.by + (int)floorf(y_b) + hi;
+      } else {
+        okc = 0;
+      }
+    }
+    sh.kind[tid] = kind;
+  }
 #pragma unroll
-    for (int m = kMaxAnchors / 2; m >= 1; m >>= 1) {
-      imn = min(imn, __shfl_xor(imn, m, 64));
-      imx = max(imx, __shfl_xor(imx, m, 64));
-      jmn = min(jmn, __shfl_xor(jmn, m, 64));
-      jmx = max(jmx, __shfl_xor(jmx, m, 64));
-    }
-    const unsigned long long any = __ballot(t != 0), bad = __ballot(okc == 0),
-                             anch = __ballot(tid < nA && kind == 0);
-    if (tid == 0) {
-      sh.touch = any != 0ull;
-      sh.cells_ok = bad == 0ull;
-      sh.box_ok = bad == 0ull;
-      sh.all_model = anch == 0ull;
-      sh.box[0] = imn;
-      sh.box[1] = imx;
-      sh.box[2] = jmn;
-      sh.box[3] = jmx;
-    }
+  for (int m = kMaxAnchors / 2; m >= 1; m >>= 1) {
+    imn = min(imn, __shfl_xor(imn, m, 64));
+    imx = max(imx, __shfl_xor(imx, m, 64));
+    jmn = min(jmn, __shfl_xor(jmn, m, 64));
+    jmx = max(jmx, __shfl_xor(jmx, m, 64));
   }
-  __syncthreads();
-
-  const bool vec = vector_stores_ok(P, G);
-  const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
-  if (!sh.touch && G.allow_skip) {
-    sink.template uncovered<NP>(P, G, tile);
-    return;
+  const unsigned long long any = __ballot(t != 0), bad = __ballot(okc == 0),
+                           anch = __ballot(tid < T.nA && kind == 0);
+  if (tid == 0) {
+    sh.touch = any != 0ull;
+    sh.cells_ok = bad == 0ull;
+    sh.box_ok = bad == 0ull;
+    sh.all_model = anch == 0ull;
+    sh.box[0] = imn;
+    sh.box[1] = imx;
+    sh.box[2] = jmn;
+    sh.box[3] = jmx;
   }
+}
 
-  // ---- 2. stage the box (asynchronous)
+// The staged source box of a tile (phase 2), from the flags tile_cells set.
+struct TileBox {
+  int bi0, bi1, bj0, bj1;  // the box clamped to the source
+  int bw, bh, lp;          // its size and LDS row stride
+  bool use_lds;            // staged (fits the LDS budget)
+  bool interior;           // no per-pixel checks needed
+  bool all_model;          // every cell has a certified model
+  bool touch;              // some cell can reach the source
+};
+
+template <int NP>
+__device__ __forceinline__ TileBox tile_box(const FramePlan &P, const TileGeom &G,
+                                            const TileXY &T, const FwdShared &sh, int lds_cap) {
+  TileBox B;
+  const int W = P.src_w, Hs = P.src_h;
   const int bu0 = sh.box[0], bu1 = sh.box[1], bu2 = sh.box[2], bu3 = sh.box[3];
-  const int bi0 = max(bu0, 0), bi1 = min(bu1, W - 1), bj0 = max(bu2, 0), bj1 = min(bu3, Hs - 1);
-  const bool box_ok = sh.box_ok && bi0 <= bi1 && bj0 <= bj1;
-  const int bw = box_ok ? bi1 - bi0 + 1 : 0, bh = box_ok ? bj1 - bj0 + 1 : 0;
-  const int lp = lds_pitch(bw);  // padded row stride (bank spread)
-  const bool use_lds = box_ok && (int64_t)lp * bh <= (int64_t)G.lds_cap;
-  const bool interior = use_lds && sh.cells_ok && P.t_order == 0 && bu0 == bi0 && bu1 == bi1 &&
-                        bu2 == bj0 && bu3 == bj1 && x0 + TW <= G.out_w && y0 + TH <= G.out_h;
-  if (use_lds) dma_box(P, bi0, bj0, bw, bh, lp, lds);
+  B.bi0 = max(bu0, 0);
+  B.bi1 = min(bu1, W - 1);
+  B.bj0 = max(bu2, 0);
+  B.bj1 = min(bu3, Hs - 1);
+  const bool box_ok = sh.box_ok && B.bi0 <= B.bi1 && B.bj0 <= B.bj1;
+  B.bw = box_ok ? B.bi1 - B.bi0 + 1 : 0;
+  B.bh = box_ok ? B.bj1 - B.bj0 + 1 : 0;
+  B.lp = lds_pitch(B.bw);  // padded row stride (bank spread)
+  B.use_lds = box_ok && (int64_t)B.lp * B.bh <= (int64_t)lds_cap;
+  B.interior = B.use_lds && sh.cells_ok && P.t_order == 0 && bu0 == B.bi0 && bu1 == B.bi1 &&
+               bu2 == B.bj0 && bu3 == B.bj1 && T.x0 + T.TW <= G.out_w && T.y0 + T.TH <= G.out_h;
+  B.all_model = sh.all_model;
+  B.touch = sh.touch;
+  return B;
+}
 
-  // ---- 3. positions: the cell's model, or FP32 offsets from its anchor
+// FP32 source positions of a thread's pixels relative to the box.
+template <int NP>
+struct FwdPos {
+  float rx[NP][kRun], ry[NP][kRun];
+  int abx[NP], aby[NP];  // cell base position minus the box origin, per run
+  unsigned valid;        // bit k * kRun + e: pixel (k, e) has a position
+};
+
+// Phase 3: every pixel's position from its cell's model or anchor (sh.cell).
+template <int INTERP, int SORD, int NP>
+__device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeom &G,
+                                               const TileXY &T, const FwdShared &sh,
+                                               const TileBox &B, FwdPos<NP> &R) {
+  constexpr bool TSIP = SORD == kRtOrder;
   const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
   const float hc = (float)kHalfCell;
-  float rx[NP][kRun], ry[NP][kRun];
-  int abx[NP], aby[NP];
-  unsigned valid = 0u;
-  if (sh.all_model && interior && !G.debug) {
+  const int xr = T.xr;
+  R.valid = 0u;
+  if (B.all_model && B.interior && !G.debug) {
     // certified cubic models throughout, tile inside the output: every pixel
     // is valid
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-      const int y = y0 + ty + k * RP;
-      const CellModel &M = sh.cell[((y >> kCellLog2) - cy0) * ncx + ((xr >> kCellLog2) - cx0)].model;
-      abx[k] = M.bx - bi0;
-      aby[k] = M.by - bj0;
-      ModelRow R;
-      model_row(M, (float)(y & (kCell - 1)) - hc, R);
+      const int y = T.y0 + T.ty + k * T.RP;
+      const CellModel &M = sh.cell[((y >> kCellLog2) - T.cy0) * T.ncx + ((xr >> kCellLog2) - T.cx0)].model;
+      R.abx[k] = M.bx - B.bi0;
+      R.aby[k] = M.by - B.bj0;
+      ModelRow Rw;
+      model_row(M, (float)(y & (kCell - 1)) - hc, Rw);
       const float a0 = (float)(xr & (kCell - 1)) - hc;
 #pragma unroll
       for (int e = 0; e < kRun; ++e) {
         float px, py;
-        model_at(R, a0 + (float)e, px, py);
+        model_at(Rw, a0 + (float)e, px, py);
         if constexpr (INTERP == DFR_NEAREST) {
           // a rounding decision within reach of the FP32 error: decide in FP64
           float tx_ = px - floorf(px), ty_ = py - floorf(py);
@@ -299,24 +356,24 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
             nearest_exact<SORD, TSIP>(P, xr + e, y, M.bx, M.by, px, py, xs, ys);
           }
         }
-        rx[k][e] = px;
-        ry[k][e] = py;
+        R.rx[k][e] = px;
+        R.ry[k][e] = py;
       }
     }
-    valid = ~0u;
+    R.valid = ~0u;
   } else {
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-      const int y = y0 + ty + k * RP;
-      const int ci = ((y >> kCellLog2) - cy0) * ncx + ((xr >> kCellLog2) - cx0);
+      const int y = T.y0 + T.ty + k * T.RP;
+      const int ci = ((y >> kCellLog2) - T.cy0) * T.ncx + ((xr >> kCellLog2) - T.cx0);
       const bool mk = sh.kind[ci] != 0;
       const Anchor &A = sh.cell[ci].anchor;
       const CellModel &M = sh.cell[ci].model;
       const int bx = mk ? M.bx : A.bx, by = mk ? M.by : A.by;
-      abx[k] = bx - bi0;
-      aby[k] = by - bj0;
-      ModelRow R;
-      if (mk) model_row(M, (float)(y & (kCell - 1)) - hc, R);
+      R.abx[k] = bx - B.bi0;
+      R.aby[k] = by - B.bj0;
+      ModelRow Rw;
+      if (mk) model_row(M, (float)(y & (kCell - 1)) - hc, Rw);
       const float dy = (float)(y & (kCell - 1));
       const float a0 = (float)(xr & (kCell - 1)) - hc;
 #pragma unroll
@@ -325,7 +382,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
         float px, py;
         bool ok;
         if (mk) {
-          model_at(R, a0 + (float)e, px, py);
+          model_at(Rw, a0 + (float)e, px, py);
           ok = true;
         } else {
           ok = pixel_position<SORD, TSIP>(P, A, tinv, sinv, (float)((xr & (kCell - 1)) + e), dy,
@@ -342,35 +399,44 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
             exact = ok;
           }
         }
-        rx[k][e] = px;
-        ry[k][e] = py;
+        R.rx[k][e] = px;
+        R.ry[k][e] = py;
         if (G.debug) debug_position(G, x, y, ok, exact, dbx, dby, bx, by, px, py);
-        if (ok) valid |= 1u << (k * kRun + e);
+        if (ok) R.valid |= 1u << (k * kRun + e);
       }
     }
   }
+}
 
-  // ---- 4. gather
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
+// Phase 4: interpolation from the staged box (the caller has waited for its
+// DMA and synchronised), results to the sink.
+template <int INTERP, int NP, class Sink>
+__device__ __forceinline__ void tile_gather(const FramePlan &P, const TileGeom &G,
+                                            const TileXY &T, const TileBox &B,
+                                            const float *__restrict__ lds, const FwdPos<NP> &R,
+                                            Sink &sink) {
   constexpr int SPAN = TapSupport<INTERP>::lo + TapSupport<INTERP>::hi;
+  const int W = P.src_w, Hs = P.src_h;
+  const int xr = T.xr, lp = B.lp;
+  const bool vec = vector_stores_ok(P, G);
+  const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
   // Interior tiles need no per-pixel check: the box holds every tap by the
-  // rigorous margin of the anchors' linear models.
-  const bool fast = interior && valid == ~0u;
+  // rigorous margin of the cells' models.
+  const bool fast = B.interior && R.valid == ~0u;
   const float a = G.cubic_a;
   if (fast) {
     // box-relative tap coordinates: unmasked LDS reads from one base address
     // per pixel, footprint exactly 1
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-      const int y = y0 + ty + k * RP;
+      const int y = T.y0 + T.ty + k * T.RP;
       float o[kRun], f[kRun];
 #pragma unroll
       for (int e = 0; e < kRun; ++e) {
         int i0, j0;
         float t_, s_;
-        tap_origin<INTERP>(rx[k][e], abx[k], i0, t_);
-        tap_origin<INTERP>(ry[k][e], aby[k], j0, s_);
+        tap_origin<INTERP>(R.rx[k][e], R.abx[k], i0, t_);
+        tap_origin<INTERP>(R.ry[k][e], R.aby[k], j0, s_);
         // i0, j0 >= 0 inside the box: one 24-bit multiply-add per pixel
         const float *__restrict__ b = lds + __umul24(j0, lp) + i0;
         auto fl = [&](int i, int j) -> float { return b[j * lp + i]; };
@@ -392,23 +458,24 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   }
   // general path: source coordinates, zero padding, footprint normalisation;
   // taps come from LDS when the pixel's in-image taps are inside the box
+  const int bi0 = B.bi0, bi1 = B.bi1, bj0 = B.bj0, bj1 = B.bj1;
   auto fl = [&](int i, int j) -> float { return lds[__umul24(j - bj0, lp) + (i - bi0)]; };
   auto fg = [&](int i, int j) -> float { return global_ptr(P.src)[(int64_t)j * P.pitch + i]; };
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    const int y = y0 + ty + k * RP;
+    const int y = T.y0 + T.ty + k * T.RP;
     if (y >= G.out_h || xr >= G.out_w) continue;
     float o[kRun], f[kRun];
 #pragma unroll
     for (int e = 0; e < kRun; ++e) {
       o[e] = miss;
       f[e] = 0.0f;
-      if (valid & (1u << (k * kRun + e))) {
+      if (R.valid & (1u << (k * kRun + e))) {
         int i0, j0;
         float t_, s_;
-        tap_origin<INTERP>(rx[k][e], abx[k] + bi0, i0, t_);
-        tap_origin<INTERP>(ry[k][e], aby[k] + bj0, j0, s_);
-        const bool in_lds = use_lds && max(i0, 0) >= bi0 && min(i0 + SPAN, W - 1) <= bi1 &&
+        tap_origin<INTERP>(R.rx[k][e], R.abx[k] + bi0, i0, t_);
+        tap_origin<INTERP>(R.ry[k][e], R.aby[k] + bj0, j0, s_);
+        const bool in_lds = B.use_lds && max(i0, 0) >= bi0 && min(i0 + SPAN, W - 1) <= bi1 &&
                             max(j0, 0) >= bj0 && min(j0 + SPAN, Hs - 1) <= bj1;
         float ov, fv;
         if (in_lds)
@@ -423,6 +490,26 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
     }
     sink.row(P, G, k, (int64_t)y * G.out_w + xr, xr, vec, false, o, f);
   }
+}
+
+// One tile of one frame: the four phases in order.
+template <int INTERP, int SORD, int NP, class Sink>
+__device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom &G, int tile,
+                                             float *__restrict__ lds, FwdShared &sh, Sink &sink) {
+  const TileXY T = tile_xy<NP>(G, tile);
+  if ((threadIdx.x >> 6) == 0) tile_cells<INTERP, SORD, NP>(P, G, T, sh);
+  __syncthreads();
+  if (!sh.touch && G.allow_skip) {
+    sink.template uncovered<NP>(P, G, tile);
+    return;
+  }
+  const TileBox B = tile_box<NP>(P, G, T, sh, G.lds_cap);
+  if (B.use_lds) dma_box(P, B.bi0, B.bj0, B.bw, B.bh, B.lp, lds);
+  FwdPos<NP> R;
+  tile_positions<INTERP, SORD, NP>(P, G, T, sh, B, R);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  tile_gather<INTERP, NP>(P, G, T, B, lds, R, sink);
 }
 
 }  // namespace dfr
