@@ -32,7 +32,7 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
   if constexpr (INTERP == DFR_NEAREST) {
     int i = bx + (int)rintf(rx), j = by + (int)rintf(ry);
     bool in = ((unsigned)i < (unsigned)W) && ((unsigned)j < (unsigned)H);
-    if (in) scatter(i, j, g);
+    if (in) scatter(0, 0, i, j, g);
     return in;
   } else {
     constexpr int NT = INTERP == DFR_BILINEAR ? 2 : 4;
@@ -80,7 +80,7 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
           float v = fetch(i0 + k, j0 + l);
           row = fmaf(wx[k], v, row);
           rowd = fmaf(dx[k], v, rowd);
-          scatter(i0 + k, j0 + l, c * wx[k] * wy[l]);
+          scatter(k, l, i0 + k, j0 + l, c * wx[k] * wy[l]);
         }
       }
       S = fmaf(wy[l], row, S);
@@ -95,7 +95,17 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
   }
 }
 
-template <int INTERP, int SORD, int NP, bool TSIP>
+// A lane's value from the lane CTRL selects within its row of 16 lanes
+// (row_shr:1 = 0x111: lane i - 1; row_shl:1 = 0x101: lane i + 1); 0 where
+// that lane is outside the row.
+template <int CTRL>
+__device__ __forceinline__ int dpp_row(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+// SRC: the source gradient is wanted (gsrc non-null); without it the kernel
+// carries no scatter code at all.
+template <int INTERP, int SORD, int NP, bool TSIP, bool SRC>
 __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom G,
                                                           const float *__restrict__ gout,
                                                           float *__restrict__ gsrc,
@@ -119,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
     const int bw = T.empty ? 0 : T.bi1 - T.bi0 + 1;
     const int bh = T.empty ? 0 : T.bj1 - T.bj0 + 1;
     const int lp = lds_pitch(bw);  // padded row stride (bank spread)
-    const bool want_src = gsrc != nullptr;
+    constexpr bool want_src = SRC;
     const bool use_lds = !T.empty && (want_src ? 2 : 1) * (int64_t)lp * bh <= (int64_t)G.lds_cap;
     float *vals = lds;
     float *gacc = lds + (use_lds ? lp * bh : 0);
@@ -133,17 +143,52 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
     const int bi0 = T.bi0, bj0 = T.bj0;
     auto fetch_lds = [&](int i, int j) -> float { return vals[(j - bj0) * lp + (i - bi0)]; };
     auto fetch_glb = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
-    auto scat_lds = [&](int i, int j, float v) {
+    auto scat_lds = [&](int, int, int i, int j, float v) {
       if (want_src) atomicAdd(&gacc[(j - bj0) * lp + (i - bi0)], v);
     };
-    auto scat_glb = [&](int i, int j, float v) {
+    auto scat_glb = [&](int, int, int i, int j, float v) {
       if (want_src) atomicAdd(&gsrc[(int64_t)j * gpitch + i], v);
     };
     const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
     const float S_s = (float)P.s_scale;
+    // Source-gradient window of a run: when the kRun pixels' tap origins
+    // lie in one row and step by exactly one column (the common case near
+    // unit scale) with every tap inside the source and the box, their
+    // NT x NT taps overlap on NT x (NT + kRun - 1) source pixels; the
+    // contributions are summed there in registers (static indices) and added
+    // to LDS once per window entry instead of once per tap (LDS float
+    // atomics are the cost of this kernel).  Other runs add per tap.
+    constexpr int NT = INTERP == DFR_BICUBIC ? 4 : 2;
+    constexpr int WC = NT + kRun - 1;
+    constexpr int OFF = INTERP == DFR_BICUBIC ? 1 : 0;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
       const int y = c.y0 + c.ty + k * c.RP;
+      int wi0 = 0, wj0 = 0;
+      bool win = false;
+      if constexpr (INTERP != DFR_NEAREST) {
+        if (use_lds && want_src && (T.valid >> (k * kRun) & ((1u << kRun) - 1)) == (1u << kRun) - 1) {
+          win = true;
+#pragma unroll
+          for (int e = 0; e < kRun; ++e) {
+            // the tap origin exactly as interp_backward derives it
+            const int i0 = T.abx[k] + (int)floorf(T.rx[k][e]) - OFF;
+            const int j0 = T.aby[k] + (int)floorf(T.ry[k][e]) - OFF;
+            if (e == 0) {
+              wi0 = i0;
+              wj0 = j0;
+            }
+            win = win && i0 == wi0 + e && j0 == wj0;
+          }
+          win = win && wi0 >= max(bi0, 0) && wi0 + WC - 1 <= min(T.bi1, W - 1) &&
+                wj0 >= max(bj0, 0) && wj0 + NT - 1 <= min(T.bj1, Hs - 1);
+        }
+      }
+      float wacc[NT][WC];
+#pragma unroll
+      for (int l = 0; l < NT; ++l)
+#pragma unroll
+        for (int m = 0; m < WC; ++m) wacc[l][m] = 0.0f;
 #pragma unroll
       for (int e = 0; e < kRun; ++e) {
         if (!(T.valid & (1u << (k * kRun + e)))) continue;
@@ -152,7 +197,11 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
         if (g == 0.0f) continue;
         float gx, gy;
         bool cov;
-        if (use_lds)
+        auto scat_win = [&](int kk, int ll, int, int, float v) { wacc[ll][e + kk] += v; };
+        if (win)
+          cov = interp_backward<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs,
+                                        G.cubic_a, g, fetch_lds, scat_win, gx, gy);
+        else if (use_lds)
           cov = interp_backward<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs,
                                         G.cubic_a, g, fetch_lds, scat_lds, gx, gy);
         else
@@ -201,9 +250,36 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
           }
         }
       }
+      if constexpr (SRC && INTERP != DFR_NEAREST) {
+        // Windows of neighbouring lanes abut in the source when the right
+        // one starts kRun columns later in the same row: its first NT - 1
+        // columns are the left one's last.  Each lane hands those columns
+        // to the lane on its right (within a DPP row), which adds them to
+        // its own when the geometry matches; the left lane then skips them.
+        // Every window entry is added to LDS exactly once.
+        const int rwi = dpp_row<0x111>(wi0), rwj = dpp_row<0x111>(wj0);
+        const bool take = win && dpp_row<0x111>(win ? 1 : 0) != 0 && rwi + kRun == wi0 && rwj == wj0;
+#pragma unroll
+        for (int l = 0; l < NT; ++l)
+#pragma unroll
+          for (int m = 0; m < NT - 1; ++m) {
+            const float t = __builtin_bit_cast(
+                float, dpp_row<0x111>(__builtin_bit_cast(int, wacc[l][kRun + m])));
+            if (take) wacc[l][m] += t;
+          }
+        const bool given = dpp_row<0x101>(take ? 1 : 0) != 0;
+        if (win) {
+          float *wb = gacc + (wj0 - bj0) * lp + (wi0 - bi0);
+#pragma unroll
+          for (int l = 0; l < NT; ++l)
+#pragma unroll
+            for (int m = 0; m < WC; ++m)
+              if ((m < kRun || !given) && wacc[l][m] != 0.0f) atomicAdd(wb + l * lp + m, wacc[l][m]);
+        }
+      }
     }
     __syncthreads();
-    if (use_lds && gsrc) {
+    if (SRC && use_lds) {
       const int wave = tid >> 6, lane = tid & 63;
       for (int r = wave; r < bh; r += kThreads / 64)
         for (int col = lane; col < bw; col += 64) {
@@ -229,24 +305,28 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
 
 using BwdKernel = void (*)(FramePlan, TileGeom, const float *, float *, int64_t, double *);
 
-template <int INTERP, int NP, bool TSIP>
+template <int INTERP, int NP, bool TSIP, bool SRC>
 static BwdKernel bwd_sord(int sord) {
   switch (sord) {
-    case 0: return reproject_bwd<INTERP, 0, NP, TSIP>;
-    case 1: return reproject_bwd<INTERP, 1, NP, TSIP>;
-    case 2: return reproject_bwd<INTERP, 2, NP, TSIP>;
-    case 3: return reproject_bwd<INTERP, 3, NP, TSIP>;
-    case 4: return reproject_bwd<INTERP, 4, NP, TSIP>;
-    default: return reproject_bwd<INTERP, 5, NP, TSIP>;
+    case 0: return reproject_bwd<INTERP, 0, NP, TSIP, SRC>;
+    case 1: return reproject_bwd<INTERP, 1, NP, TSIP, SRC>;
+    case 2: return reproject_bwd<INTERP, 2, NP, TSIP, SRC>;
+    case 3: return reproject_bwd<INTERP, 3, NP, TSIP, SRC>;
+    case 4: return reproject_bwd<INTERP, 4, NP, TSIP, SRC>;
+    default: return reproject_bwd<INTERP, 5, NP, TSIP, SRC>;
   }
 }
 
 // The backward kernel runs 1 or 2 rows per thread (the host picks such
 // tiles); the target SIP is compiled in only where the target has one.
 template <int INTERP>
-static BwdKernel bwd_pick(int np, int sord, bool tsip) {
-  if (tsip) return np == 1 ? bwd_sord<INTERP, 1, true>(sord) : bwd_sord<INTERP, 2, true>(sord);
-  return np == 1 ? bwd_sord<INTERP, 1, false>(sord) : bwd_sord<INTERP, 2, false>(sord);
+static BwdKernel bwd_pick(int np, int sord, bool tsip, bool src) {
+  if (src) {
+    if (tsip) return np == 1 ? bwd_sord<INTERP, 1, true, true>(sord) : bwd_sord<INTERP, 2, true, true>(sord);
+    return np == 1 ? bwd_sord<INTERP, 1, false, true>(sord) : bwd_sord<INTERP, 2, false, true>(sord);
+  }
+  if (tsip) return np == 1 ? bwd_sord<INTERP, 1, true, false>(sord) : bwd_sord<INTERP, 2, true, false>(sord);
+  return np == 1 ? bwd_sord<INTERP, 1, false, false>(sord) : bwd_sord<INTERP, 2, false, false>(sord);
 }
 
 hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, int np,
@@ -254,9 +334,10 @@ hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, in
                            double *partials, hipStream_t stream) {
   if (G.n_tiles <= 0) return hipSuccess;
   const bool tsip = P.t_order > 0;
-  BwdKernel k = interp == DFR_NEAREST    ? bwd_pick<DFR_NEAREST>(np, P.s_order, tsip)
-                : interp == DFR_BILINEAR ? bwd_pick<DFR_BILINEAR>(np, P.s_order, tsip)
-                                         : bwd_pick<DFR_BICUBIC>(np, P.s_order, tsip);
+  const bool src = grad_src != nullptr;
+  BwdKernel k = interp == DFR_NEAREST    ? bwd_pick<DFR_NEAREST>(np, P.s_order, tsip, src)
+                : interp == DFR_BILINEAR ? bwd_pick<DFR_BILINEAR>(np, P.s_order, tsip, src)
+                                         : bwd_pick<DFR_BICUBIC>(np, P.s_order, tsip, src);
   size_t lds = (size_t)G.lds_cap * sizeof(float);
   hipLaunchKernelGGL(k, dim3(G.n_tiles), dim3(kThreads), lds, stream, P, G, grad_out, grad_src,
                      gsrc_pitch, partials);
