@@ -268,13 +268,38 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
             if (take) wacc[l][m] += t;
           }
         const bool given = dpp_row<0x101>(take ? 1 : 0) != 0;
+        // The same along columns: the lane one output row below (lane +
+        // 2^lg, same run) whose window starts one source row lower shares
+        // NT - 1 rows of the first kRun columns.  Passed down the wave's
+        // rows in order (a chain, so each lane forwards what it received),
+        // through the lane crossbar, not LDS atomics.
+        const int lg = G.txt_log2;
+        const int lane = threadIdx.x & 63, vstep = 1 << lg, vrow = lane >> lg;
+        bool given_v = false;
+        if (vstep < 64) {
+          const int uwi = __shfl_up(wi0, vstep), uwj = __shfl_up(wj0, vstep);
+          const bool uwin = __shfl_up(win ? 1 : 0, vstep) != 0;
+          const bool take_v = win && uwin && vrow > 0 && uwi == wi0 && uwj + 1 == wj0;
+          for (int r = 1; r < (64 >> lg); ++r) {
+#pragma unroll
+            for (int l = 0; l < NT - 1; ++l)
+#pragma unroll
+              for (int m = 0; m < kRun; ++m) {
+                const float t = __shfl_up(wacc[l + 1][m], vstep);
+                if (take_v && vrow == r) wacc[l][m] += t;
+              }
+          }
+          given_v = __shfl_down(take_v ? 1 : 0, vstep) != 0 && vrow < (64 >> lg) - 1;
+        }
         if (win) {
           float *wb = gacc + (wj0 - bj0) * lp + (wi0 - bi0);
 #pragma unroll
           for (int l = 0; l < NT; ++l)
 #pragma unroll
-            for (int m = 0; m < WC; ++m)
-              if ((m < kRun || !given) && wacc[l][m] != 0.0f) atomicAdd(wb + l * lp + m, wacc[l][m]);
+            for (int m = 0; m < WC; ++m) {
+              const bool mine = m < kRun ? (l == 0 || !given_v) : !given;
+              if (mine && wacc[l][m] != 0.0f) atomicAdd(wb + l * lp + m, wacc[l][m]);
+            }
         }
       }
     }
