@@ -8,14 +8,14 @@ float32, inputs resident in HBM.  One step = one full forward pass over the
 frame through the C ABI: host set-up, the per-cell position-model prepass and
 the tile kernel (two launches on the caller's stream).
 
-Beside it: the roofline of the step (algorithmic bytes per step over the
-step's average duration from HIP events on its stream, against 8 TB/s; the
-step is the two launches, so this bounds the tile kernel's own fraction from
-below), the HBM traffic the committed rocprofv3 PMC summary measured,
-the FP64 CPU oracle timed on this host, and the other forms of the path
-(nearest and bicubic, the FP64 and trigonometric forms, forward+backward on
-the 2048^2 alignment case, the 64-frame batch and its coadd, the +89.5 deg
-precision case).
+Beside it: the roofline of the dominant kernel, the tile kernel
+(algorithmic bytes per launch over its average duration, HIP events on its
+stream around launches of that kernel alone through a plan that holds the
+frame's cell models, against 8 TB/s), the same for the whole step, the HBM
+traffic the committed rocprofv3 PMC summary measured, the FP64 CPU oracle
+timed on this host, and the other forms of the path (nearest and bicubic,
+the FP64 and trigonometric forms, forward+backward on the 2048^2 alignment
+case, the 64-frame batch and its coadd, the +89.5 deg precision case).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras]
                     [--no-cpu-baseline] [--calibrate-copy] [--sweep]
@@ -125,6 +125,28 @@ def time_steps(fn, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return e0.elapsed_time(e1) / steps, wall
+
+
+def time_tile_kernel(dfr, frame, case, steps, warmup):
+    """Average duration of the tile kernel alone over `steps` launches: a
+    plan holds the frame's cell models, each dfr_plan_execute is one launch
+    (raw C calls with prebuilt arguments, alternating the frame's buffer
+    sets like the step)."""
+    from paper_2505_03932_amd import api
+    plan = api.Plan(case.src.shape, case.src_wcs, case.tgt_wcs, case.out_shape, "bilinear")
+    lib, stream, k = api._lib, frame.stream, [0]
+
+    def launch():
+        s, o, f = frame.sets[k[0] % len(frame.sets)]
+        k[0] += 1
+        st = lib.dfr_plan_execute(plan._handle, s.data_ptr(), s.stride(0), o.data_ptr(),
+                                  f.data_ptr(), stream)
+        if st != 0:
+            raise RuntimeError(f"dfr_plan_execute failed: {st}")
+
+    ms, _ = time_steps(launch, steps, warmup)
+    plan.close()
+    return ms
 
 
 def touched_source_pixels(dfr, src_t, sw, tw, shape, interp):
@@ -339,14 +361,23 @@ def main():
     touched = touched_source_pixels(dfr, src_t, case.src_wcs, case.tgt_wcs, case.out_shape,
                                     "bilinear")
     alg_bytes = 8 * npx + 4 * touched
-    achieved = alg_bytes / ms / 1e6  # GB/s
+    # the dominant kernel alone: the same frame through a plan (models made
+    # once), so each timed launch is exactly one reproject_tiles
+    kms = time_tile_kernel(dfr, frame, case, args.steps, args.warmup)
+    achieved = alg_bytes / kms / 1e6  # GB/s
+    step_gbs = alg_bytes / ms / 1e6
     traffic = stored_profile("reproject_sip3_bilinear_pmc.md", "traffic")
     split = stored_profile("reproject_sip3_bilinear_kernel_trace.md", "split")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": (traffic or {}).get("bytes_per_launch"),
-            "alg_bytes_per_launch": alg_bytes, "step_ms": round(ms, 5),
-            "launches": "cell_models_kernel + reproject_tiles (HIP events around both)",
+            "alg_bytes_per_launch": alg_bytes, "kernel": "reproject_tiles",
+            "kernel_ms": round(kms, 5),
+            "timing": "HIP events on the launch stream around the timed launches of the tile "
+                      "kernel alone (dfr_plan_execute)",
+            "step_ms": round(ms, 5), "step_gbs": round(step_gbs, 1),
+            "step_frac": round(step_gbs / HBM_PEAK_GBS, 4),
+            "step_launches": "cell_models_kernel + reproject_tiles",
             "touched_src_px": touched}
     if split:
         # the tile kernel alone, from the committed kernel trace of this command

@@ -117,6 +117,38 @@ dfr_status dfr_reproject(const float *src, int32_t src_h, int32_t src_w, int64_t
                          float *out, float *footprint, const dfr_options *opt,
                          void *stream);
 
+/* A reprojection geometry prepared once for many images of the same shape
+ * and WCS pair (a time series on fixed pointing, repeated reprojection of
+ * model images): the FP64 set-up of section 3.2 and the per-cell position
+ * models are computed once, into device memory the plan owns (about 112 B
+ * per 32x32 output cell), and each execute runs only the per-pixel kernel.
+ * Opaque; not thread-safe to destroy while another thread executes it. */
+typedef struct dfr_plan dfr_plan;
+
+/* Create a plan on the current device; the model prepass is enqueued on
+ * `stream` (execute on the same stream, or synchronise first).  The source
+ * pointer is not needed yet: src_h and src_w fix the shape.  Errors as for
+ * dfr_reproject; only the FP32 forms (DFR_PREC_F32, DFR_PREC_F32_ANCHOR)
+ * have plans (DFR_E_UNSUPPORTED otherwise), debug positions are refused
+ * (DFR_E_ARG), DFR_E_NOMEM when the model table cannot be allocated.
+ *   plan  host, out: the new plan (NULL on error)                         */
+dfr_status dfr_plan_create(int32_t src_h, int32_t src_w, const dfr_wcs *src_wcs,
+                           const dfr_wcs *tgt_wcs, int32_t out_h, int32_t out_w,
+                           dfr_interp interp, const dfr_options *opt, void *stream,
+                           dfr_plan **plan);
+
+/* Reproject one image with a plan: out and footprint exactly as
+ * dfr_reproject with the plan's geometry and options gives them (bit for
+ * bit).  src is device [src_h][src_pitch] float32 with the plan's shape;
+ * out device [out_h][out_w]; footprint nullable.  DFR_E_ARG when called on
+ * another device than the plan's. */
+dfr_status dfr_plan_execute(const dfr_plan *plan, const float *src, int64_t src_pitch, float *out,
+                            float *footprint, void *stream);
+
+/* Free a plan (NULL is a no-op).  Call it once the work enqueued with the
+ * plan has completed. */
+dfr_status dfr_plan_destroy(dfr_plan *plan);
+
 /* One sub-exposure of a batch (the paper's use case: many exposures stacked
  * onto one target grid, section 1). */
 typedef struct dfr_frame {

@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "DFR_OK", 1: "DFR_E_NULL", 2: "DFR_E_SHAPE", 3: "DFR_E_WCS",
                 4: "DFR_E_UNSUPPORTED", 5: "DFR_E_DEVICE", 6: "DFR_E_NOMEM", 7: "DFR_E_ARG"}
 
 EXPORTED = [
-    "dfr_options_init", "dfr_reproject", "dfr_reproject_batch", "dfr_coadd_batch",
+    "dfr_options_init", "dfr_reproject", "dfr_plan_create", "dfr_plan_execute",
+    "dfr_plan_destroy", "dfr_reproject_batch", "dfr_coadd_batch",
     "dfr_wcs_grad_size",
     "dfr_reproject_backward", "dfr_sq_residual", "dfr_autotune", "dfr_autotune_batch",
     "dfr_tile_count", "dfr_tile_shape", "dfr_cd_from_pc_cdelt", "dfr_check_wcs",
@@ -75,6 +76,12 @@ def _load():
     L.dfr_options_init.restype = None
     L.dfr_reproject.argtypes = [vp, i32, i32, i64, W, W, i32, i32, st, vp, vp, O, vp]
     L.dfr_reproject.restype = st
+    L.dfr_plan_create.argtypes = [i32, i32, W, W, i32, i32, st, O, vp, C.POINTER(vp)]
+    L.dfr_plan_create.restype = st
+    L.dfr_plan_execute.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.dfr_plan_execute.restype = st
+    L.dfr_plan_destroy.argtypes = [vp]
+    L.dfr_plan_destroy.restype = st
     L.dfr_reproject_batch.argtypes = [i32, C.POINTER(dfr_frame), W, i32, i32, st, vp, vp, O, vp]
     L.dfr_reproject_batch.restype = st
     L.dfr_coadd_batch.argtypes = [i32, C.POINTER(dfr_frame), W, i32, i32, st, vp, vp, vp, i32,
@@ -133,6 +140,22 @@ def dfr_reproject_batch(n, frames, tgt_wcs, out_h, out_w, interp, outs, footprin
                         stream) -> int:
     return lib.dfr_reproject_batch(n, frames, C.byref(tgt_wcs), out_h, out_w, interp, outs,
                                    footprints, C.byref(opt) if opt is not None else None, stream)
+
+
+def dfr_plan_create(src_h, src_w, src_wcs, tgt_wcs, out_h, out_w, interp, opt, stream):
+    """Returns (status, plan handle or None)."""
+    h = C.c_void_p()
+    s = lib.dfr_plan_create(src_h, src_w, C.byref(src_wcs), C.byref(tgt_wcs), out_h, out_w, interp,
+                            C.byref(opt) if opt is not None else None, stream, C.byref(h))
+    return s, h.value
+
+
+def dfr_plan_execute(plan, src, src_pitch, out, footprint, stream) -> int:
+    return lib.dfr_plan_execute(plan, src, src_pitch, out, footprint, stream)
+
+
+def dfr_plan_destroy(plan) -> int:
+    return lib.dfr_plan_destroy(plan)
 
 
 def dfr_coadd_batch(n, frames, tgt_wcs, out_h, out_w, interp, sum_wf, sum_f, coadd, accumulate,

@@ -4,6 +4,7 @@ PyTorch provides device memory and streams; every step of the reprojection
 runs in libdfr's HIP kernels.
 
   reproject(src, src_wcs, tgt_wcs, shape_out, order)       single image
+  Plan(src_shape, src_wcs, tgt_wcs, shape_out).execute(src) one geometry, many images
   calculate_reprojection(source_hdus, target_wcs, ...)     the paper's call
   reproject_batch(srcs, src_wcss, tgt_wcs, shape_out)      many frames
   coadd_batch(srcs, src_wcss, tgt_wcs, shape_out)          footprint-weighted stack
@@ -164,6 +165,67 @@ def reproject(src, src_wcs, tgt_wcs, shape_out=None, order="bilinear", *, footpr
     if debug_positions:
         return out, (fp if footprint else None), pos
     return out, (fp if footprint else None)
+
+
+class Plan:
+    """A reprojection geometry prepared once (``dfr_plan_create``) and run on
+    many images of its source shape (``dfr_plan_execute``): results equal
+    :func:`reproject` with the same arguments bit for bit; the per-cell
+    models are not recomputed per image."""
+
+    def __init__(self, src_shape, src_wcs, tgt_wcs, shape_out=None, order="bilinear", *,
+                 precision="f32", cubic_a=-0.5, nan_outside=False, tile=0, device=None):
+        self.src_shape = (int(src_shape[0]), int(src_shape[1]))
+        shape_out = self.src_shape if shape_out is None else shape_out
+        self.shape_out = (int(shape_out[0]), int(shape_out[1]))
+        dev = torch.device(device if device is not None else "cuda")
+        self.device = dev if dev.index is not None else torch.device("cuda", torch.cuda.current_device())
+        self._handle = None
+        sw, tw = CWcs(src_wcs), CWcs(tgt_wcs)
+        with torch.cuda.device(self.device):
+            s, h = _lib.dfr_plan_create(self.src_shape[0], self.src_shape[1], sw.s, tw.s,
+                                        self.shape_out[0], self.shape_out[1], ORDERS[order],
+                                        _opts(precision, cubic_a, nan_outside, tile),
+                                        _stream(self.device))
+        _check(s, "dfr_plan_create")
+        self._handle = h
+
+    def execute(self, src, out=None, fp=None, footprint=True):
+        """Returns (out, footprint or None) for ``src`` (the plan's shape)."""
+        if self._handle is None:
+            raise ValueError("plan is closed")
+        src = _src_tensor(src)
+        if tuple(src.shape) != self.src_shape:
+            raise ValueError(f"source shape {tuple(src.shape)} is not the plan's {self.src_shape}")
+        oh, ow = self.shape_out
+        if out is None:
+            out = torch.empty((oh, ow), dtype=torch.float32, device=src.device)
+        if footprint and fp is None:
+            fp = torch.empty((oh, ow), dtype=torch.float32, device=src.device)
+        with torch.cuda.device(src.device):
+            s = _lib.dfr_plan_execute(self._handle, src.data_ptr(), src.stride(0), _ptr(out),
+                                      _ptr(fp if footprint else None), _stream(src.device))
+        _check(s, "dfr_plan_execute")
+        return out, (fp if footprint else None)
+
+    def close(self):
+        if self._handle is not None:
+            torch.cuda.synchronize(self.device)
+            h, self._handle = self._handle, None
+            _check(_lib.dfr_plan_destroy(h), "dfr_plan_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def calculate_reprojection(source_hdus, target_wcs, shape_out=None, order="bilinear", *,

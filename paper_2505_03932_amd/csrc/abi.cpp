@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -179,6 +180,16 @@ dfr_status time_candidates(Run &run, hipStream_t st, int &best) {
 
 }  // namespace
 
+// A reprojection geometry prepared once for many images (dfr_plan_*): the
+// frame plan without its image pointers, the tile geometry, and the per-cell
+// models in device memory the plan owns.
+struct dfr_plan {
+  dfr::FramePlan P;
+  dfr::TileGeom G;
+  int interp = 0, np = 1, device = 0;
+  dfr::CellModel *models = nullptr;
+};
+
 extern "C" {
 
 void dfr_options_init(dfr_options *opt) {
@@ -272,6 +283,85 @@ dfr_status dfr_coadd_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tg
   }
   return run_batch(plans, G, (int)interp, np, max_sord, o.precision == DFR_PREC_F32, st, false,
                    &C);
+}
+
+dfr_status dfr_plan_create(int32_t src_h, int32_t src_w, const dfr_wcs *src_wcs,
+                           const dfr_wcs *tgt_wcs, int32_t out_h, int32_t out_w,
+                           dfr_interp interp, const dfr_options *opt, void *stream,
+                           dfr_plan **plan) {
+  if (!plan) return DFR_E_NULL;
+  *plan = nullptr;
+  if (!src_wcs || !tgt_wcs) return DFR_E_NULL;
+  if (src_h < 0 || src_w < 0 || out_h < 0 || out_w < 0) return DFR_E_SHAPE;
+  dfr_status s;
+  if ((s = check_wcs(src_wcs, true)) != DFR_OK) return s;
+  if ((s = check_wcs(tgt_wcs, false)) != DFR_OK) return s;
+  if (!interp_ok((int)interp)) return DFR_E_UNSUPPORTED;
+  dfr_options o;
+  if ((s = resolve_options(opt, o)) != DFR_OK) return s;
+  if (!is_f32(o)) return DFR_E_UNSUPPORTED;
+  if (o.debug_positions) return DFR_E_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DFR_E_DEVICE;
+  dfr_plan *pl = new (std::nothrow) dfr_plan();
+  if (!pl) return DFR_E_NOMEM;
+  pl->device = dev;
+  pl->interp = (int)interp;
+  build_plan(nullptr, src_h, src_w, src_w, *src_wcs, *tgt_wcs, out_h, out_w, nullptr, nullptr,
+             pl->P);
+  TileShape ts;
+  const int tile = choose_tile(pl->P, out_h, out_w, (int)interp, o.tile, false);
+  make_geom(pl->P, out_h, out_w, (int)interp, tile, o, pl->G, ts);
+  pl->np = ts.np;
+  if (o.precision == DFR_PREC_F32 && pl->P.t_order == 0 && out_h > 0 && out_w > 0) {
+    const int ncx = (out_w + kCell - 1) / kCell, ncy = (out_h + kCell - 1) / kCell;
+    if (hipMalloc(&pl->models, (size_t)ncx * ncy * sizeof(CellModel)) != hipSuccess) {
+      pl->models = nullptr;
+      delete pl;
+      return DFR_E_NOMEM;
+    }
+    pl->P.models = pl->models;
+    if (launch_cell_models(pl->P, ncx, ncy, pl->models, reinterpret_cast<hipStream_t>(stream)) !=
+        hipSuccess) {
+      (void)hipFree(pl->models);
+      delete pl;
+      return DFR_E_DEVICE;
+    }
+  }
+  *plan = pl;
+  return DFR_OK;
+}
+
+dfr_status dfr_plan_execute(const dfr_plan *plan, const float *src, int64_t src_pitch, float *out,
+                            float *footprint, void *stream) {
+  if (!plan) return DFR_E_NULL;
+  const int32_t h = plan->P.src_h, w = plan->P.src_w;
+  if (h > 0 && w > 0) {
+    if (!src) return DFR_E_NULL;
+    if (src_pitch < w) return DFR_E_SHAPE;
+  }
+  if (plan->G.out_h == 0 || plan->G.out_w == 0) return DFR_OK;
+  if (!out) return DFR_E_NULL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return DFR_E_DEVICE;
+  if (dev != plan->device) return DFR_E_ARG;
+  FramePlan P = plan->P;
+  P.src = (h > 0 && w > 0) ? src : nullptr;
+  P.pitch = src_pitch;
+  P.out = out;
+  P.fp = footprint;
+  return launch_forward_f32(P, plan->G, plan->interp, plan->np,
+                            reinterpret_cast<hipStream_t>(stream)) == hipSuccess
+             ? DFR_OK
+             : DFR_E_DEVICE;
+}
+
+dfr_status dfr_plan_destroy(dfr_plan *plan) {
+  if (!plan) return DFR_OK;
+  dfr_status s = DFR_OK;
+  if (plan->models && hipFree(plan->models) != hipSuccess) s = DFR_E_DEVICE;
+  delete plan;
+  return s;
 }
 
 dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w,

@@ -157,6 +157,20 @@ def test_batch_backward_loss_errors(L):
     assert L.dfr_coadd_batch(1, frames, T.s, 4, 4, 1, 1, 1, None, 0, o, None) == 4
     assert L.dfr_coadd_batch(1, frames, T.s, -4, 4, 1, 1, 1, None, 0, None, None) == 2
     assert L.dfr_coadd_batch(1, frames, T.s, 0, 4, 1, None, None, None, 0, None, None) == 0
+    # plans: argument errors before any device work
+    raw = L.lib
+    assert raw.dfr_plan_create(8, 8, C.byref(S.s), C.byref(T.s), 4, 4, 1, None, None, None) == 1
+    h = C.c_void_p()
+    assert raw.dfr_plan_create(8, 8, None, C.byref(T.s), 4, 4, 1, None, None, C.byref(h)) == 1
+    assert raw.dfr_plan_create(-8, 8, C.byref(S.s), C.byref(T.s), 4, 4, 1, None, None,
+                               C.byref(h)) == 2
+    assert raw.dfr_plan_create(8, 8, C.byref(S.s), C.byref(T.s), 4, 4, 3, None, None,
+                               C.byref(h)) == 4
+    assert raw.dfr_plan_create(8, 8, C.byref(S.s), C.byref(T.s), 4, 4, 1, C.byref(o), None,
+                               C.byref(h)) == 4  # FP64 form: no plan
+    assert h.value is None
+    assert raw.dfr_plan_execute(None, 1, 8, 1, None, None) == 1
+    assert raw.dfr_plan_destroy(None) == 0
     # backward: FP32 only, inverse SIP order <= 5, gradient input required
     assert L.dfr_reproject_backward(1, 8, 8, 8, S.s, T.s, 4, 4, 1, None, None, None, None,
                                     None) == 1
