@@ -143,7 +143,7 @@ dfr_status prepare_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_
     std::lock_guard<std::mutex> lk(tune_mutex_for_batch());
     tile = tuned_tile(batch_key(plans, out_h, out_w, interp, max_sord));
   }
-  if (tile == 0) tile = stack ? kCoaddTile : kDefaultTile;
+  if (tile == 0) tile = stack ? kCoaddTile : choose_tile(plans[0], out_h, out_w, interp, 0, true);
   batch_geom(plans, out_h, out_w, interp, tile, o, G, np);
   return DFR_OK;
 }

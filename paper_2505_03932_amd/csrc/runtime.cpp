@@ -122,8 +122,22 @@ int choose_tile(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, in
       if (it != g_tune.end()) return it->second;
     }
   }
-  // heuristic: 64x32 when its source box fits the LDS budget, else the
-  // largest tile whose box does
+  // heuristic: the forward's measured default for the interpolation unless
+  // the map turns its source box much larger per output pixel than the 64x32
+  // tile's (a rotated map and a flat tile); then 64x32 (also the backward's,
+  // lds_factor 2) when its box fits the LDS budget, else the largest tile
+  // whose box does
+  if (lds_factor == 1) {
+    const int pref = forward_default_tile(interp);
+    TileShape a, b;
+    tile_shape(pref, a);
+    tile_shape(kDefaultTile, b);
+    const double na = lds_need(P, out_h, out_w, interp, pref);
+    const double nb = lds_need(P, out_h, out_w, interp, kDefaultTile);
+    if (na <= kLdsMaxFloats &&
+        na / (a.width * a.height) <= 1.25 * nb / (b.width * b.height))
+      return pref;
+  }
   if (lds_factor * lds_need(P, out_h, out_w, interp, kDefaultTile) <= kLdsMaxFloats)
     return kDefaultTile;
   const int order[] = {4, 8, 1, 7, 10};
