@@ -389,7 +389,8 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
   TileShape ts;
   std::memset(&G, 0, sizeof(G));
   if (out_h > 0 && out_w > 0) {
-    int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false, 2);
+    int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false, 2,
+                           backward_default_tile((int)interp, grad_src != nullptr));
     TileShape t4;
     // the backward kernel runs 1 or 2 rows per thread: 4-row tiles use
     // their 2-row sibling of the same width

@@ -17,6 +17,12 @@ constexpr int kCoaddTile = 5;    // coadd default
 // measured on the 6000x4000 SIP-3 frame: 128 x 16 for nearest and bilinear,
 // 32 x 64 for bicubic.
 inline int forward_default_tile(int interp) { return interp == DFR_BICUBIC ? 2 : 8; }
+// The backward's, measured on the 2048^2 bicubic and 6000x4000 bilinear
+// cases: 64 x 16 (one row per thread) for bicubic with the source gradient
+// (its LDS adds), else 64 x 32.
+inline int backward_default_tile(int interp, bool src_grad) {
+  return interp == DFR_BICUBIC && src_grad ? 4 : kDefaultTile;
+}
 
 struct TileShape {
   int txt_log2;  // threads per tile row, log2

@@ -112,7 +112,7 @@ void tune_store(const std::string &key, int tile) {
 }
 
 int choose_tile(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, int requested,
-                bool batch, int lds_factor) {
+                bool batch, int lds_factor, int pref) {
   if (requested >= 1 && requested <= kTileCount) return requested;
   {
     std::lock_guard<std::mutex> lk(g_tune_mutex);
@@ -122,20 +122,19 @@ int choose_tile(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, in
       if (it != g_tune.end()) return it->second;
     }
   }
-  // heuristic: the forward's measured default for the interpolation unless
-  // the map turns its source box much larger per output pixel than the 64x32
-  // tile's (a rotated map and a flat tile); then 64x32 (also the backward's,
-  // lds_factor 2) when its box fits the LDS budget, else the largest tile
-  // whose box does
-  if (lds_factor == 1) {
-    const int pref = forward_default_tile(interp);
+  // heuristic: the measured default for the kernel and interpolation unless
+  // the map turns its source box much larger per output pixel than the
+  // 64x32 tile's (a rotated map and a flat tile); then 64x32 when its box
+  // fits the LDS budget, else the largest tile whose box does
+  {
+    if (pref < 1 || pref > kTileCount) pref = forward_default_tile(interp);
     TileShape a, b;
     tile_shape(pref, a);
     tile_shape(kDefaultTile, b);
     const double na = lds_need(P, out_h, out_w, interp, pref);
     const double nb = lds_need(P, out_h, out_w, interp, kDefaultTile);
-    if (na <= kLdsMaxFloats &&
-        na / (a.width * a.height) <= 1.25 * nb / (b.width * b.height))
+    if (lds_factor * na <= kLdsMaxFloats &&
+        na / (a.width * a.height) <= 1.5 * nb / (b.width * b.height))
       return pref;
   }
   if (lds_factor * lds_need(P, out_h, out_w, interp, kDefaultTile) <= kLdsMaxFloats)

@@ -16,8 +16,10 @@ constexpr int kLdsMaxFloats = 16384;  // 64 KiB of LDS per work-group for staged
 
 // Tile for a reprojection: `requested` if nonzero, else the tuned cache
 // entry for this kind of map, else a heuristic that fits the LDS budget.
+// pref: the untuned shape to try first (0: the forward's default for the
+// interpolation).
 int choose_tile(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, int requested,
-                bool batch, int lds_factor = 1);
+                bool batch, int lds_factor = 1, int pref = 0);
 
 // Key under which tuned tiles are cached: kind, interpolation, SIP order and
 // coarse classes of the map's magnification and rotation.
