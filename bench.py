@@ -228,8 +228,9 @@ def extra_grad(dfr, steps):
 
 
 def extra_batch(dfr, steps):
-    """64 uneven frames onto one 8192^2 grid in one graph-replayed launch, and
-    the same frames coadded (footprint-weighted sums, no per-frame output)."""
+    """64 uneven frames onto one 8192^2 grid in one graph-replayed launch, the
+    same frames into per-frame windows (the boxes each frame can cover), and
+    coadded (footprint-weighted sums, no per-frame output)."""
     import torch
     from synth import configs
     t0 = time.perf_counter()
@@ -251,6 +252,35 @@ def extra_batch(dfr, steps):
                                      "gbs_alg": round(byts / ms / 1e6, 1),
                                      "hbm_frac": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)}}
     del outs, fps
+    torch.cuda.empty_cache()
+    # the same stack into per-frame windows (the boxes each frame can cover)
+    from paper_2505_03932_amd import api
+    import ctypes as C
+    boxes = dfr.batch_boxes(srcs, c.src_wcs, c.tgt_wcs, c.out_shape, "bilinear")
+    couts = [torch.empty((int(b[3]), int(b[2])), dtype=torch.float32, device="cuda") for b in boxes]
+    cfps = [torch.empty_like(t) for t in couts]
+    n = len(srcs)
+    frames, keep = api._frames(srcs, c.src_wcs)
+    tw, opts = api.CWcs(c.tgt_wcs), api._opts("f32")
+    optrs = (C.c_void_p * n)(*[t.data_ptr() for t in couts])
+    fptrs = (C.c_void_p * n)(*[t.data_ptr() for t in cfps])
+    bptr = boxes.ctypes.data_as(C.c_void_p)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def cropped():
+        st = api._lib.dfr_reproject_batch_cropped(n, frames, tw.s, oh, ow, 1, bptr, optrs, fptrs,
+                                                  opts, stream)
+        if st != 0:
+            raise RuntimeError(f"dfr_reproject_batch_cropped failed: {st}")
+
+    ms_x, _ = time_steps(cropped, max(2, steps // 2), 1)
+    crop_px = int(sum(int(b[2]) * int(b[3]) for b in boxes))
+    byts_x = 8 * crop_px + src_bytes
+    res["batch64_8192_bilinear_cropped"] = {
+        "ms": round(ms_x, 3), "window_px": crop_px, "window_mpix_s": round(crop_px / ms_x / 1e3, 1),
+        "dense_equiv_mpix_s": round(npx / ms_x / 1e3, 1), "gbs_alg": round(byts_x / ms_x / 1e6, 1),
+        "hbm_frac": round(byts_x / ms_x / 1e6 / HBM_PEAK_GBS, 4)}
+    del couts, cfps
     torch.cuda.empty_cache()
     # the same stack coadded: sources read once, three target images written
     swf = torch.empty((oh, ow), dtype=torch.float32, device="cuda")

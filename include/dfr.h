@@ -169,6 +169,30 @@ dfr_status dfr_reproject_batch(int32_t n, const dfr_frame *frames, const dfr_wcs
                                float *const *outs, float *const *footprints,
                                const dfr_options *opt, void *stream);
 
+/* The window of the target grid each frame of a batch can cover: boxes is
+ * host [n][4] = {x0, y0, w, h} in target pixels (whole 32-pixel cells,
+ * clipped to the output; w = h = 0 when no pixel can reach the frame).
+ * Every pixel outside frame i's box is uncovered in dfr_reproject_batch
+ * (the boxes come from the rigorous bounds of the model prepass, which this
+ * runs on `stream` and waits for; with a target SIP there are no models and
+ * every box is the whole grid).  Errors as for dfr_reproject_batch. */
+dfr_status dfr_batch_boxes(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_wcs,
+                           int32_t out_h, int32_t out_w, dfr_interp interp,
+                           const dfr_options *opt, void *stream, int32_t *boxes);
+
+/* dfr_reproject_batch into a window per frame: boxes is host [n][4] =
+ * {x0, y0, w, h} inside the output (DFR_E_SHAPE otherwise); outs[i] and
+ * footprints[i] (footprints or any entry nullable) are device [h][w]
+ * float32 holding target pixels x0 .. x0+w-1, y0 .. y0+h-1 of frame i,
+ * bit-identical to those pixels of dfr_reproject_batch; outs[i] may be NULL
+ * when w * h = 0.  With the boxes of dfr_batch_boxes the dense per-frame
+ * traffic of a stack shrinks to the pixels each frame can cover. */
+dfr_status dfr_reproject_batch_cropped(int32_t n, const dfr_frame *frames,
+                                       const dfr_wcs *tgt_wcs, int32_t out_h, int32_t out_w,
+                                       dfr_interp interp, const int32_t *boxes,
+                                       float *const *outs, float *const *footprints,
+                                       const dfr_options *opt, void *stream);
+
 /* Coadd (stack) n frames onto one target grid: the paper's motivating use of
  * reprojection, combining sub-exposures on a common grid (section 1), with
  * each frame weighted by its footprint (the per-pixel normalisation of

@@ -9,12 +9,12 @@ binding (``_lib``: the C entry points by name; ``api``: torch helpers).
 from . import _lib
 from ._lib import DfrError
 from .api import (Plan, ReprojectFn, Wcs, as_wcs, autotune, calculate_reprojection, cell_model,
-                  coadd_batch, release,
+                  batch_boxes, coadd_batch, release, reproject_batch_cropped,
                   reproject, reproject_backward, reproject_batch, reproject_differentiable,
                   sq_residual, wcs_from_header, wcs_params, wcs_with_params)
 
 __all__ = ["DfrError", "Plan", "ReprojectFn", "Wcs", "as_wcs", "autotune", "calculate_reprojection",
-           "cell_model", "coadd_batch",
+           "batch_boxes", "cell_model", "coadd_batch", "reproject_batch_cropped",
            "release", "reproject", "reproject_backward", "reproject_batch",
            "reproject_differentiable", "sq_residual", "wcs_from_header", "wcs_params",
            "wcs_with_params"]

@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "DFR_OK", 1: "DFR_E_NULL", 2: "DFR_E_SHAPE", 3: "DFR_E_WCS",
 
 EXPORTED = [
     "dfr_options_init", "dfr_reproject", "dfr_plan_create", "dfr_plan_execute",
-    "dfr_plan_destroy", "dfr_reproject_batch", "dfr_coadd_batch",
+    "dfr_plan_destroy", "dfr_reproject_batch", "dfr_batch_boxes", "dfr_reproject_batch_cropped",
+    "dfr_coadd_batch",
     "dfr_wcs_grad_size",
     "dfr_reproject_backward", "dfr_sq_residual", "dfr_autotune", "dfr_autotune_batch",
     "dfr_tile_count", "dfr_tile_shape", "dfr_cd_from_pc_cdelt", "dfr_check_wcs",
@@ -84,6 +85,11 @@ def _load():
     L.dfr_plan_destroy.restype = st
     L.dfr_reproject_batch.argtypes = [i32, C.POINTER(dfr_frame), W, i32, i32, st, vp, vp, O, vp]
     L.dfr_reproject_batch.restype = st
+    L.dfr_batch_boxes.argtypes = [i32, C.POINTER(dfr_frame), W, i32, i32, st, O, vp, vp]
+    L.dfr_batch_boxes.restype = st
+    L.dfr_reproject_batch_cropped.argtypes = [i32, C.POINTER(dfr_frame), W, i32, i32, st, vp, vp,
+                                              vp, O, vp]
+    L.dfr_reproject_batch_cropped.restype = st
     L.dfr_coadd_batch.argtypes = [i32, C.POINTER(dfr_frame), W, i32, i32, st, vp, vp, vp, i32,
                                   O, vp]
     L.dfr_coadd_batch.restype = st
@@ -156,6 +162,18 @@ def dfr_plan_execute(plan, src, src_pitch, out, footprint, stream) -> int:
 
 def dfr_plan_destroy(plan) -> int:
     return lib.dfr_plan_destroy(plan)
+
+
+def dfr_batch_boxes(n, frames, tgt_wcs, out_h, out_w, interp, opt, stream, boxes) -> int:
+    return lib.dfr_batch_boxes(n, frames, C.byref(tgt_wcs), out_h, out_w, interp,
+                               C.byref(opt) if opt is not None else None, stream, boxes)
+
+
+def dfr_reproject_batch_cropped(n, frames, tgt_wcs, out_h, out_w, interp, boxes, outs, footprints,
+                                opt, stream) -> int:
+    return lib.dfr_reproject_batch_cropped(n, frames, C.byref(tgt_wcs), out_h, out_w, interp,
+                                           boxes, outs, footprints,
+                                           C.byref(opt) if opt is not None else None, stream)
 
 
 def dfr_coadd_batch(n, frames, tgt_wcs, out_h, out_w, interp, sum_wf, sum_f, coadd, accumulate,

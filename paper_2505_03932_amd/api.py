@@ -7,6 +7,7 @@ runs in libdfr's HIP kernels.
   Plan(src_shape, src_wcs, tgt_wcs, shape_out).execute(src) one geometry, many images
   calculate_reprojection(source_hdus, target_wcs, ...)     the paper's call
   reproject_batch(srcs, src_wcss, tgt_wcs, shape_out)      many frames
+  reproject_batch_cropped(srcs, src_wcss, tgt_wcs, shape)  per-frame windows (batch_boxes)
   coadd_batch(srcs, src_wcss, tgt_wcs, shape_out)          footprint-weighted stack
   ReprojectFn / reproject_differentiable(...)              autograd
   sq_residual(out, ref, mask)                              alignment loss
@@ -284,6 +285,54 @@ def reproject_batch(srcs: Sequence[torch.Tensor], src_wcss, tgt_wcs, shape_out, 
                                  _stream(dev))
     _check(s, "dfr_reproject_batch")
     return outs, (fps if footprint else None)
+
+
+def batch_boxes(srcs: Sequence[torch.Tensor], src_wcss, tgt_wcs, shape_out, order="bilinear", *,
+                cubic_a=-0.5):
+    """[n, 4] int array of (x0, y0, w, h): the window of the target grid each
+    frame can cover (outside it a frame's batch output is uncovered)."""
+    srcs = [_src_tensor(s) for s in srcs]
+    n = len(srcs)
+    boxes = np.zeros((n, 4), dtype=np.int32)
+    if n == 0:
+        return boxes
+    frames, keep = _frames(srcs, src_wcss)
+    tw = CWcs(tgt_wcs)
+    s = _lib.dfr_batch_boxes(n, frames, tw.s, int(shape_out[0]), int(shape_out[1]), ORDERS[order],
+                             _opts("f32", cubic_a), _stream(srcs[0].device),
+                             boxes.ctypes.data_as(C.c_void_p))
+    _check(s, "dfr_batch_boxes")
+    return boxes
+
+
+def reproject_batch_cropped(srcs: Sequence[torch.Tensor], src_wcss, tgt_wcs, shape_out,
+                            order="bilinear", *, boxes=None, footprint=True, cubic_a=-0.5,
+                            nan_outside=False, tile=0):
+    """The batch with one window per frame (default: :func:`batch_boxes`).
+    Returns (outs, fps, boxes): frame i's [h, w] crops of target pixels
+    x0 .. x0+w-1, y0 .. y0+h-1, and the [n, 4] boxes used."""
+    srcs = [_src_tensor(s) for s in srcs]
+    oh, ow = int(shape_out[0]), int(shape_out[1])
+    if boxes is None:
+        boxes = batch_boxes(srcs, src_wcss, tgt_wcs, shape_out, order, cubic_a=cubic_a)
+    boxes = np.ascontiguousarray(boxes, dtype=np.int32).reshape(len(srcs), 4)
+    dev = srcs[0].device if srcs else torch.device("cuda")
+    outs = [torch.empty((int(b[3]), int(b[2])), dtype=torch.float32, device=dev) for b in boxes]
+    fps = [torch.empty((int(b[3]), int(b[2])), dtype=torch.float32, device=dev)
+           for b in boxes] if footprint else None
+    n = len(srcs)
+    if n == 0:
+        return outs, fps, boxes
+    frames, keep = _frames(srcs, src_wcss)
+    out_ptrs = (C.c_void_p * n)(*[o.data_ptr() if o.numel() else None for o in outs])
+    fp_ptrs = (C.c_void_p * n)(*[f.data_ptr() if f.numel() else None for f in fps]) \
+        if footprint else None
+    tw = CWcs(tgt_wcs)
+    s = _lib.dfr_reproject_batch_cropped(n, frames, tw.s, oh, ow, ORDERS[order],
+                                         boxes.ctypes.data_as(C.c_void_p), out_ptrs, fp_ptrs,
+                                         _opts("f32", cubic_a, nan_outside, tile), _stream(dev))
+    _check(s, "dfr_reproject_batch_cropped")
+    return outs, fps, boxes
 
 
 def coadd_batch(srcs: Sequence[torch.Tensor], src_wcss, tgt_wcs, shape_out, order="bilinear",

@@ -281,8 +281,104 @@ dfr_status dfr_coadd_batch(int32_t n, const dfr_frame *frames, const dfr_wcs *tg
                ? DFR_OK
                : DFR_E_DEVICE;
   }
+  BatchRun run;
+  run.coadd = &C;
   return run_batch(plans, G, (int)interp, np, max_sord, o.precision == DFR_PREC_F32, st, false,
-                   &C);
+                   run);
+}
+
+dfr_status dfr_batch_boxes(int32_t n, const dfr_frame *frames, const dfr_wcs *tgt_wcs,
+                           int32_t out_h, int32_t out_w, dfr_interp interp,
+                           const dfr_options *opt, void *stream, int32_t *boxes) {
+  if (n > 0 && !boxes) return DFR_E_NULL;
+  std::vector<FramePlan> plans;
+  int tile = 0, np = 0, max_sord = 0;
+  TileGeom G;
+  dfr_status s = prepare_batch(n, frames, tgt_wcs, out_h, out_w, (int)interp, nullptr, nullptr,
+                               opt, plans, G, tile, np, max_sord, true);
+  if (s != DFR_OK) return s;
+  if (plans.empty() || G.n_tiles == 0) {
+    for (int i = 0; i < 4 * n; ++i) boxes[i] = 0;
+    return DFR_OK;
+  }
+  dfr_options o;
+  resolve_options(opt, o);
+  std::vector<int32_t> reach(4 * (size_t)n);
+  BatchRun run;
+  run.reach_host = reach.data();
+  if ((s = run_batch(plans, G, (int)interp, np, max_sord, o.precision == DFR_PREC_F32,
+                     reinterpret_cast<hipStream_t>(stream), false, run)) != DFR_OK)
+    return s;
+  for (int i = 0; i < n; ++i) {
+    const int32_t *r = &reach[4 * (size_t)i];
+    int32_t *b = boxes + 4 * (size_t)i;
+    if (r[0] == -1) {  // no model table: the whole grid
+      b[0] = b[1] = 0;
+      b[2] = out_w;
+      b[3] = out_h;
+    } else if (r[1] == 0) {  // no cell reaches the source
+      b[0] = b[1] = b[2] = b[3] = 0;
+    } else {
+      const int64_t x0 = (int64_t)(kReachBig - r[0]) * kCell, y0 = (int64_t)(kReachBig - r[2]) * kCell;
+      const int64_t x1 = std::min<int64_t>((int64_t)r[1] * kCell, out_w);
+      const int64_t y1 = std::min<int64_t>((int64_t)r[3] * kCell, out_h);
+      b[0] = (int32_t)x0;
+      b[1] = (int32_t)y0;
+      b[2] = (int32_t)std::max<int64_t>(x1 - x0, 0);
+      b[3] = (int32_t)std::max<int64_t>(y1 - y0, 0);
+    }
+  }
+  return DFR_OK;
+}
+
+dfr_status dfr_reproject_batch_cropped(int32_t n, const dfr_frame *frames,
+                                       const dfr_wcs *tgt_wcs, int32_t out_h, int32_t out_w,
+                                       dfr_interp interp, const int32_t *boxes,
+                                       float *const *outs, float *const *footprints,
+                                       const dfr_options *opt, void *stream) {
+  if (n > 0 && (!boxes || !outs)) return DFR_E_NULL;
+  for (int i = 0; i < n; ++i) {
+    const int32_t *b = boxes + 4 * (size_t)i;
+    if (b[0] < 0 || b[1] < 0 || b[2] < 0 || b[3] < 0 || (int64_t)b[0] + b[2] > out_w ||
+        (int64_t)b[1] + b[3] > out_h)
+      return DFR_E_SHAPE;
+    if ((int64_t)b[2] * b[3] > 0 && !outs[i]) return DFR_E_NULL;
+  }
+  std::vector<FramePlan> plans;
+  int tile = 0, np = 0, max_sord = 0;
+  TileGeom G;
+  dfr_status s = prepare_batch(n, frames, tgt_wcs, out_h, out_w, (int)interp, nullptr, nullptr,
+                               opt, plans, G, tile, np, max_sord, true);
+  if (s != DFR_OK || plans.empty() || G.n_tiles == 0) return s;
+  // each frame's window and the range of global tiles that meet it
+  TileShape ts;
+  tile_shape(tile, ts);
+  int64_t items = 0;
+  for (int i = 0; i < n; ++i) {
+    const int32_t *b = boxes + 4 * (size_t)i;
+    FramePlan &P = plans[i];
+    P.out = outs[i];
+    P.fp = footprints ? footprints[i] : nullptr;
+    P.crop[0] = b[0];
+    P.crop[1] = b[1];
+    P.crop[2] = b[2];
+    P.crop[3] = b[3];
+    P.item0 = (int32_t)items;
+    P.tile0[0] = b[0] / ts.width;
+    P.tile0[1] = b[1] / ts.height;
+    P.ntx = 1;
+    if ((int64_t)b[2] * b[3] == 0) continue;
+    const int tx1 = (b[0] + b[2] - 1) / ts.width, ty1 = (b[1] + b[3] - 1) / ts.height;
+    P.ntx = tx1 - P.tile0[0] + 1;
+    items += (int64_t)P.ntx * (ty1 - P.tile0[1] + 1);
+    if (items > 0x7fffffffLL) return DFR_E_SHAPE;
+  }
+  dfr_options o;
+  resolve_options(opt, o);
+  BatchRun run;
+  run.crop_items = items;
+  return run_batch(plans, G, (int)interp, np, max_sord, o.precision == DFR_PREC_F32,
+                   reinterpret_cast<hipStream_t>(stream), false, run);
 }
 
 dfr_status dfr_plan_create(int32_t src_h, int32_t src_w, const dfr_wcs *src_wcs,

@@ -66,6 +66,10 @@ struct FramePlan {
   int32_t pad_;
   const CellModel *models;  // device table of per-cell position models, or null
   int32_t *reach;           // batch: the frame's reach box of cells (see kReachBig), or null
+  int32_t crop[4];          // x0, y0, w, h of the frame's output window (full grid unless cropped)
+  int32_t item0;            // cropped batch: first work item of the frame
+  int32_t tile0[2];         // cropped batch: first tile column and row of the window
+  int32_t ntx;              // cropped batch: tile columns of the window
   double tA[kMaxCoef], tB[kMaxCoef];   // FP64 coefficients, packed by tri9
   double sA[kMaxCoef], sB[kMaxCoef];
   float ftA[kMaxCoef], ftB[kMaxCoef];  // FP32, scaled: c * S^(p+q)
@@ -452,7 +456,11 @@ __device__ __forceinline__ void compute_anchor(const FramePlan &P, int xa, int y
   double my = 2.0 * kCell * (fabs((double)A.f1) + fabs((double)A.f2)) * (1.0 + 2.0 * L) + 8.0 + support;
   bool outside = (xs < -mx) || (xs > (double)(P.src_w - 1) + mx) || (ys < -my) ||
                  (ys > (double)(P.src_h - 1) + my);
-  A.touch = (w > 0.0 && kk < 0.5 && L < 0.25 && outside && P.t_order == 0) ? 0 : 1;
+  // none can when the cell maps outside the source, or when w < 0 at the
+  // anchor and, with kk < 1/2, everywhere in the cell (every direction is
+  // behind the source tangent plane: no pixel has a position)
+  const bool away = (w > 0.0 && kk < 0.5 && L < 0.25 && outside) || (w < 0.0 && kk < 0.5);
+  A.touch = (away && P.t_order == 0) ? 0 : 1;
   if (P.src_h <= 0 || P.src_w <= 0) A.touch = 0;
 }
 

@@ -63,11 +63,16 @@ __global__ __launch_bounds__(64) void cell_models_batch_kernel(const FramePlan *
     out[i] = M;
     // can any pixel of the cell have a tap inside the source?  From the
     // model's range over the whole cell, grown by 4 px (more than any tap
-    // support and the tile kernel's guard); without a model: assume so
+    // support and the tile kernel's guard); without a model, the anchor's
+    // rigorous test with the widest support
     reach = 1;
     if (P.src_w <= 0 || P.src_h <= 0) {
       reach = 0;
-    } else if (M.certified) {
+    } else if (!M.certified) {
+      Anchor A;
+      compute_anchor<SORD, false>(P, cx * kCell, cy * kCell, 4, A);
+      reach = A.touch;
+    } else {
       const float h = (float)kHalfCell;
       const float rx = (fabsf(M.mx[4]) + fabsf(M.mx[1])) * h + M.ex + 4.0f;
       const float ry = (fabsf(M.my[4]) + fabsf(M.my[1])) * h + M.ey + 4.0f;

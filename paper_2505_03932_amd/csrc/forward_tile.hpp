@@ -114,10 +114,12 @@ struct StoreSink {
   __device__ __forceinline__ void uncovered(const FramePlan &P, const TileGeom &G, int tile) {
     tile_uncovered<NP>(P, G, tile);
   }
-  // row k of the thread's runs; `full`: every footprint is exactly 1
-  __device__ __forceinline__ void row(const FramePlan &P, const TileGeom &G, int k, int64_t off,
+  // run k of the thread (output row y, columns xr ..); `full`: every
+  // footprint is exactly 1
+  __device__ __forceinline__ void row(const FramePlan &P, const TileGeom &G, int k, int y,
                                       int xr, bool vec, bool full, const float o[kRun],
                                       const float f[kRun]) {
+    const int64_t off = (int64_t)y * G.out_w + xr;
     store_run(P.out, off, xr, G.out_w, vec, o);
     if (P.fp) store_run(P.fp, off, xr, G.out_w, vec, f);
   }
@@ -129,8 +131,8 @@ struct StackSink {
   float w[NP][kRun];  // sum of F
   template <int NP_>
   __device__ __forceinline__ void uncovered(const FramePlan &, const TileGeom &, int) {}
-  __device__ __forceinline__ void row(const FramePlan &, const TileGeom &, int k, int64_t, int,
-                                      bool, bool full, const float o[kRun], const float f[kRun]) {
+  __device__ __forceinline__ void row(const FramePlan &, const TileGeom &, int k, int, int, bool,
+                                      bool full, const float o[kRun], const float f[kRun]) {
 #pragma unroll
     for (int e = 0; e < kRun; ++e) {
       if (full) {
@@ -140,6 +142,35 @@ struct StackSink {
         s[k][e] = fmaf(o[e], f[e], s[k][e]);
         w[k][e] += f[e];
       }
+    }
+  }
+};
+
+// Writes into the frame's window (cropped batch): P.out and P.fp are
+// [crop h][crop w] arrays of the target pixels x0 .. x0+w-1, y0 .. y0+h-1;
+// pixels of the tile outside the window are not stored.
+struct CropSink {
+  template <int NP>
+  __device__ __forceinline__ void uncovered(const FramePlan &P, const TileGeom &G, int tile);
+  __device__ __forceinline__ void row(const FramePlan &P, const TileGeom &G, int, int y, int xr,
+                                      bool, bool, const float o[kRun], const float f[kRun]) {
+    const int cx = P.crop[0], cy = P.crop[1], cw = P.crop[2], ch = P.crop[3];
+    if (y < cy || y >= cy + ch || xr + kRun <= cx || xr >= cx + cw) return;
+    const int rx = xr - cx;
+    const int64_t off = (int64_t)(y - cy) * cw + rx;
+    const bool vec = rx >= 0 && rx + kRun <= cw && ((rx | cw) & (kRun - 1)) == 0 &&
+                     ((reinterpret_cast<uintptr_t>(P.out) & 15) == 0) &&
+                     (P.fp == nullptr || (reinterpret_cast<uintptr_t>(P.fp) & 15) == 0);
+    if (vec) {
+      store_run(P.out, off, 0, kRun, true, o);
+      if (P.fp) store_run(P.fp, off, 0, kRun, true, f);
+      return;
+    }
+#pragma unroll
+    for (int e = 0; e < kRun; ++e) {
+      if (rx + e < 0 || rx + e >= cw) continue;
+      __builtin_nontemporal_store(o[e], global_ptr(P.out) + off + e);
+      if (P.fp) __builtin_nontemporal_store(f[e], global_ptr(P.fp) + off + e);
     }
   }
 };
@@ -452,7 +483,7 @@ __device__ __forceinline__ void tile_gather(const FramePlan &P, const TileGeom &
         }
         f[e] = 1.0f;
       }
-      sink.row(P, G, k, (int64_t)y * G.out_w + xr, xr, vec, true, o, f);
+      sink.row(P, G, k, y, xr, vec, true, o, f);
     }
     return;
   }
@@ -488,8 +519,24 @@ __device__ __forceinline__ void tile_gather(const FramePlan &P, const TileGeom &
         }
       }
     }
-    sink.row(P, G, k, (int64_t)y * G.out_w + xr, xr, vec, false, o, f);
+    sink.row(P, G, k, y, xr, vec, false, o, f);
   }
+}
+
+// A tile of a cropped frame no pixel of which reaches the source.
+template <int NP>
+__device__ __forceinline__ void CropSink::uncovered(const FramePlan &P, const TileGeom &G,
+                                                    int tile) {
+  const TileXY T = tile_xy<NP>(G, tile);
+  const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
+  float zo[kRun], zf[kRun];
+#pragma unroll
+  for (int e = 0; e < kRun; ++e) {
+    zo[e] = miss;
+    zf[e] = 0.0f;
+  }
+#pragma unroll
+  for (int k = 0; k < NP; ++k) row(P, G, k, T.y0 + T.ty + k * T.RP, T.xr, false, false, zo, zf);
 }
 
 // One tile of one frame: the four phases in order.

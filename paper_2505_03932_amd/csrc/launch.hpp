@@ -63,6 +63,11 @@ hipError_t launch_batch_f32(const FramePlan *plans_dev, int n_frames, int max_so
                             const TileGeom &G, int interp, int np, int *counter,
                             int grid, hipStream_t stream);
 const void *batch_kernel_ptr(int interp, int np, int sord);
+// The batch into per-frame windows (FramePlan crop, item0, tile0, ntx):
+// `total` items over the frames, persistent grid as the batch.
+hipError_t launch_batch_cropped(const FramePlan *plans_dev, int n_frames, int total, int max_sord,
+                                const TileGeom &G, int interp, int np, int *counter, int grid,
+                                hipStream_t stream);
 // Coadd of a frame table: one work-group per target tile (G.n_tiles).
 hipError_t launch_coadd_f32(const FramePlan *plans_dev, int n_frames, int max_sord,
                             const TileGeom &G, int interp, int np, const CoaddOut &C,

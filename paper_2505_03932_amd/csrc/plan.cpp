@@ -126,6 +126,8 @@ void build_plan(const float *src, int32_t src_h, int32_t src_w, int64_t pitch,
                 const dfr_wcs &sw, const dfr_wcs &tw, int32_t out_h, int32_t out_w, float *out,
                 float *fp, FramePlan &P) {
   std::memset(&P, 0, sizeof(P));
+  P.crop[2] = out_w;
+  P.crop[3] = out_h;
   double Ms[9], Mt[9], R[9], At[9], Asi[9], T[9];
   tangent_frame(sw.crval[0], sw.crval[1], Ms);
   tangent_frame(tw.crval[0], tw.crval[1], Mt);

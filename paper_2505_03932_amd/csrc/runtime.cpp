@@ -235,8 +235,9 @@ void release_workspaces() {
 
 dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int interp, int np,
                      int max_sord, bool models, hipStream_t stream, bool graph,
-                     const CoaddOut *coadd) {
-  if (coadd) graph = false;  // its output pointers are kernel arguments
+                     const BatchRun &run) {
+  const CoaddOut *coadd = run.coadd;
+  if (coadd || run.crop_items >= 0 || run.reach_host) graph = false;
   std::lock_guard<std::mutex> lk(g_ws_mutex);
   Workspace *w = workspace(stream);
   if (!w) return DFR_E_DEVICE;
@@ -297,9 +298,24 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
     if (models && hipLaunchKernel(cell_models_batch_ptr(max_sord), mgrid, dim3(64), margs, 0,
                                   stream) != hipSuccess)
       return DFR_E_DEVICE;
+    if (run.reach_host) {
+      // the reach boxes the prepass recorded, back to the host (no model
+      // table: every frame may reach everywhere, reported as -1)
+      if (!models) {
+        for (int i = 0; i < 4 * n; ++i) run.reach_host[i] = -1;
+      } else if (hipMemcpyAsync(run.reach_host, reach, (size_t)16 * n, hipMemcpyDeviceToHost,
+                                stream) != hipSuccess ||
+                 hipStreamSynchronize(stream) != hipSuccess) {
+        return DFR_E_DEVICE;
+      }
+      return DFR_OK;
+    }
     const hipError_t e =
         coadd ? launch_coadd_f32(plans_dev, n, max_sord, G, interp, np, *coadd, stream)
-              : launch_batch_f32(plans_dev, n, max_sord, G, interp, np, counter, grid, stream);
+        : run.crop_items >= 0
+            ? launch_batch_cropped(plans_dev, n, (int)run.crop_items, max_sord, G, interp, np,
+                                   counter, grid, stream)
+            : launch_batch_f32(plans_dev, n, max_sord, G, interp, np, counter, grid, stream);
     if (e != hipSuccess) return DFR_E_DEVICE;
   } else {
     BatchGraph *found = nullptr;

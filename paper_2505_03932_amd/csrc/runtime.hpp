@@ -64,12 +64,20 @@ Workspace *workspace(hipStream_t stream);
 void *workspace_buffer(Workspace *w, size_t bytes);
 void release_workspaces();
 
+// What a batch run produces besides the default per-frame outputs.
+struct BatchRun {
+  const CoaddOut *coadd = nullptr;  // stack the frames into these sums
+  int64_t crop_items = -1;          // >= 0: per-frame windows, this many work items
+  int32_t *reach_host = nullptr;    // only the model prepass: its reach boxes, 4 per frame
+};
+
 // Reproject a batch in one persistent launch; `graph` replays a cached HIP
 // graph (frame-table copy, per-cell models of every frame when `models`,
-// counter reset, persistent kernel).  With `coadd` the frames are stacked
-// into its sums instead (eager launches, one work-group per target tile).
+// counter reset, persistent kernel).  The coadd, cropped and reach-only
+// runs launch eagerly (their output pointers are kernel arguments, or the
+// host waits).
 dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int interp, int np,
                      int max_sord, bool models, hipStream_t stream, bool graph,
-                     const CoaddOut *coadd = nullptr);
+                     const BatchRun &run = BatchRun());
 
 }  // namespace dfr

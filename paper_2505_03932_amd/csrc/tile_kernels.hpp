@@ -65,6 +65,52 @@ void reproject_batch(const FramePlan *__restrict__ plans, int n_frames, TileGeom
   }
 }
 
+// The batch into per-frame windows of the target grid (cropped outputs):
+// frame i has items item0 .. item0 + (tiles of its window) - 1, the tiles of
+// the global tile grid that meet its window, so every pixel is computed
+// exactly as in the full batch; only the window's pixels are stored.
+template <int INTERP, int SORD, int NP>
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(NP >= 4 ? 4 : 5)))
+void reproject_batch_cropped(const FramePlan *__restrict__ plans, int n_frames, int total,
+                             TileGeom G, int *__restrict__ counter) {
+  extern __shared__ float lds[];
+  __shared__ FwdShared sh;
+  using ConstPlan = const __attribute__((address_space(4))) FramePlan;
+  int next = 0, end = 0;
+  while (true) {
+    if (threadIdx.x == 0) {
+      if (next >= end) {
+        next = atomicAdd(counter, kBatchChunk);
+        end = next + kBatchChunk;
+      }
+      sh.item = next++;
+    }
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(sh.item);
+    if (item >= total) break;  // uniform: the group leaves together
+    // the last frame whose first item is <= item (frames without items share
+    // the next frame's item0 and are passed over)
+    int lo = 0, hi = n_frames - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (((ConstPlan *)(plans + mid))->item0 <= item)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const FramePlan &P = *(const FramePlan *)((ConstPlan *)(plans + lo));
+    const int k = item - P.item0;
+    const int tile = (P.tile0[1] + k / P.ntx) * G.tiles_x + P.tile0[0] + k % P.ntx;
+    CropSink sink;
+    if (tile_out_of_reach<NP>(P, G, tile))
+      sink.uncovered<NP>(P, G, tile);
+    else
+      forward_tile<INTERP, SORD, NP>(P, G, tile, lds, sh, sink);
+    __syncthreads();
+  }
+}
+
 // Coadd (stacking) of many frames onto one target grid, the paper's
 // motivating use (section 1): per target pixel the sums over the frames of
 // out * F and of F, and their ratio.  One work-group owns one target tile for
@@ -154,6 +200,10 @@ struct BatchK {
 };
 
 template <int INTERP, int SORD, int NP>
+struct CropK {
+  static const void *ptr() { return reinterpret_cast<const void *>(reproject_batch_cropped<INTERP, SORD, NP>); }
+};
+template <int INTERP, int SORD, int NP>
 struct CoaddK {
   static const void *ptr() { return reinterpret_cast<const void *>(coadd_tiles<INTERP, SORD, NP>); }
 };
@@ -178,6 +228,15 @@ const void *batch_kernel_for(int np, int sord) {
 }
 
 template <int INTERP>
+const void *crop_kernel_for(int np, int sord) {
+  switch (np) {
+    case 1: return pick_sord<CropK, INTERP, 1>(sord);
+    case 2: return pick_sord<CropK, INTERP, 2>(sord);
+    default: return pick_sord<CropK, INTERP, 4>(sord);
+  }
+}
+
+template <int INTERP>
 const void *coadd_kernel_for(int np, int sord) {
   switch (np) {
     case 1: return pick_sord<CoaddK, INTERP, 1>(sord);
@@ -192,6 +251,9 @@ extern template const void *tile_kernel_for<DFR_BICUBIC>(int, int);
 extern template const void *batch_kernel_for<DFR_NEAREST>(int, int);
 extern template const void *batch_kernel_for<DFR_BILINEAR>(int, int);
 extern template const void *batch_kernel_for<DFR_BICUBIC>(int, int);
+extern template const void *crop_kernel_for<DFR_NEAREST>(int, int);
+extern template const void *crop_kernel_for<DFR_BILINEAR>(int, int);
+extern template const void *crop_kernel_for<DFR_BICUBIC>(int, int);
 extern template const void *coadd_kernel_for<DFR_NEAREST>(int, int);
 extern template const void *coadd_kernel_for<DFR_BILINEAR>(int, int);
 extern template const void *coadd_kernel_for<DFR_BICUBIC>(int, int);

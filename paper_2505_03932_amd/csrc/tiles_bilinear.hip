@@ -5,4 +5,5 @@ namespace dfr {
 template const void *tile_kernel_for<DFR_BILINEAR>(int, int);
 template const void *batch_kernel_for<DFR_BILINEAR>(int, int);
 template const void *coadd_kernel_for<DFR_BILINEAR>(int, int);
+template const void *crop_kernel_for<DFR_BILINEAR>(int, int);
 }  // namespace dfr

@@ -157,6 +157,19 @@ def test_batch_backward_loss_errors(L):
     assert L.dfr_coadd_batch(1, frames, T.s, 4, 4, 1, 1, 1, None, 0, o, None) == 4
     assert L.dfr_coadd_batch(1, frames, T.s, -4, 4, 1, 1, 1, None, 0, None, None) == 2
     assert L.dfr_coadd_batch(1, frames, T.s, 0, 4, 1, None, None, None, 0, None, None) == 0
+    # cropped batch and boxes: the same frame checks, boxes inside the output
+    bx = (C.c_int32 * 4)(0, 0, 2, 2)
+    assert L.dfr_batch_boxes(1, frames, T.s, 4, 4, 1, None, None, None) == 1
+    assert L.dfr_batch_boxes(-1, frames, T.s, 4, 4, 1, None, None, bx) == 7
+    assert L.dfr_reproject_batch_cropped(1, frames, T.s, 4, 4, 1, None, outs, None, None, None) == 1
+    assert L.dfr_reproject_batch_cropped(1, frames, T.s, 4, 4, 1, bx, None, None, None, None) == 1
+    bad = (C.c_int32 * 4)(3, 0, 2, 2)  # x0 + w > out_w
+    assert L.dfr_reproject_batch_cropped(1, frames, T.s, 4, 4, 1, bad, outs, None, None, None) == 2
+    neg = (C.c_int32 * 4)(0, -1, 2, 2)
+    assert L.dfr_reproject_batch_cropped(1, frames, T.s, 4, 4, 1, neg, outs, None, None, None) == 2
+    nul = (C.c_void_p * 1)(None)
+    assert L.dfr_reproject_batch_cropped(1, frames, T.s, 4, 4, 1, bx, nul, None, None, None) == 1
+    assert L.dfr_reproject_batch_cropped(1, frames, T.s, 4, 4, 1, bx, outs, None, o, None) == 4
     # plans: argument errors before any device work
     raw = L.lib
     assert raw.dfr_plan_create(8, 8, C.byref(S.s), C.byref(T.s), 4, 4, 1, None, None, None) == 1
