@@ -1,18 +1,10 @@
-// Reprojection of one output tile (paper section 3.1: source positions by
-// the two stages of section 3.2, interpolation, footprint normalisation).
-//
-// A tile is (kRun << txt_log2) x ((kThreads >> txt_log2) * NP) output
-// pixels.  Thread (tx, ty) owns NP runs of kRun consecutive pixels in rows
-// ty, ty + RP, ..., so every wave store covers contiguous row segments.
-//
-// Two schedules share the per-pixel position code:
-//   * tile_anchors / tile_positions / stage_box (used by the backward
-//     kernel): anchors, then positions with the exact bounding box of all
-//     in-image taps (wave min/max reductions + LDS atomics), then a
-//     synchronous copy of that box into LDS;
-//   * forward_tile: anchors and a sampled source box in parallel, the box
-//     staged by asynchronous DMA while the positions are computed (see the
-//     comment above forward_tile).
+// Per-pixel building blocks of the reprojection kernels (paper section 3.1:
+// source positions by the two stages of section 3.2, interpolation,
+// footprint normalisation): the FP32 position chain from a cell's FP64
+// anchor, tap origins and interpolation weights, evaluation of a cell's
+// cubic position model, streaming row stores and the FP64 rounding decision
+// of nearest.  The forward tile body (forward_tile.hpp) and the backward
+// kernel (backward.hip) are composed from them.
 #pragma once
 
 #include "cell_model.hpp"
@@ -82,191 +74,11 @@ __device__ __forceinline__ bool pixel_position(const FramePlan &P, const Anchor 
   return (A.sgn * den > 0.0f) && (fabsf(rx) < 1.0e7f) && (fabsf(ry) < 1.0e7f);
 }
 
-// LDS scratch of a tile kernel besides the dynamic source tile.
-struct TileShared {
-  Anchor anchor[kMaxAnchors];
-  int box[4];     // imin, imax, jmin, jmax of the source box
-  int touch;      // any anchor cell can reach the source
-};
-
 template <int INTERP>
 struct TapSupport {
   static constexpr int lo = INTERP == DFR_BICUBIC ? 1 : 0;  // taps left/up of floor
   static constexpr int hi = INTERP == DFR_NEAREST ? 0 : (INTERP == DFR_BILINEAR ? 1 : 2);
 };
-
-// Geometry of a tile and of the calling thread inside it.
-struct TileCtx {
-  int x0, y0;    // tile origin (output pixels)
-  int RP;        // rows per pass
-  int cx0, cy0;  // first anchor cell
-  int ncx;       // anchor cells per tile row
-  int ty;        // thread row in the tile
-  int xr;        // first output column of the thread's runs
-};
-
-// Phase 1.  Returns false when no pixel of the tile can reach the source
-// (and skipping is allowed): the caller then only writes "uncovered".
-template <int INTERP, int SORD, bool TSIP, int NP>
-__device__ __forceinline__ bool tile_anchors(const FramePlan &P, const TileGeom &G, int tile,
-                                             TileShared &sh, TileCtx &c) {
-  const int tid = threadIdx.x;
-  const int lg = G.txt_log2;
-  const int TW = kRun << lg;
-  c.RP = kThreads >> lg;
-  const int TH = c.RP * NP;
-  const int trow = tile / G.tiles_x;
-  c.x0 = (tile - trow * G.tiles_x) * TW;
-  c.y0 = trow * TH;
-  c.cx0 = c.x0 / kCell;
-  c.ncx = TW / kCell;
-  c.cy0 = c.y0 / kCell;
-  const int ncy = TH >= kCell ? TH / kCell : 1;
-  const int nA = c.ncx * ncy;
-  c.ty = tid >> lg;
-  c.xr = c.x0 + (tid & ((1 << lg) - 1)) * kRun;
-  if (tid < 64) {
-    int t = 0;
-    if (tid < nA) {
-      int cy = c.cy0 + tid / c.ncx, cx = c.cx0 + tid % c.ncx;
-      compute_anchor<SORD, TSIP>(P, cx * kCell, cy * kCell, TapSupport<INTERP>::hi, sh.anchor[tid]);
-      t = sh.anchor[tid].touch;
-    }
-    unsigned long long any = __ballot(t != 0);
-    if (tid == 0) {
-      sh.touch = any != 0ull;
-      sh.box[0] = 0x7fffffff;
-      sh.box[1] = -0x7fffffff;
-      sh.box[2] = 0x7fffffff;
-      sh.box[3] = -0x7fffffff;
-    }
-  }
-  __syncthreads();
-  return sh.touch || !G.allow_skip;
-}
-
-template <int NP>
-struct TilePos {
-  float rx[NP][kRun], ry[NP][kRun];
-  int abx[NP], aby[NP];  // anchor base of each run
-  int aidx[NP];          // anchor index of each run
-  unsigned valid;        // bit k*kRun+e: pixel (run k, element e) has a position
-  int bi0, bi1, bj0, bj1;
-  bool empty;            // no pixel of the tile has a tap inside the source
-};
-
-// Phases 2 and 3 (ends with a barrier; the box is then known to all).
-template <int INTERP, int SORD, bool TSIP, int NP>
-__device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeom &G,
-                                               TileShared &sh, const TileCtx &c,
-                                               TilePos<NP> &T) {
-  constexpr int SLO = TapSupport<INTERP>::lo, SHI = TapSupport<INTERP>::hi;
-  const int W = P.src_w, Hs = P.src_h;
-  const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
-  int imin = 0x7fffffff, imax = -0x7fffffff, jmin = 0x7fffffff, jmax = -0x7fffffff;
-  T.valid = 0u;
-#pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    const int y = c.y0 + c.ty + k * c.RP;
-    const int a = ((y >> kCellLog2) - c.cy0) * c.ncx + ((c.xr >> kCellLog2) - c.cx0);
-    const Anchor &A = sh.anchor[a];
-    T.aidx[k] = a;
-    T.abx[k] = A.bx;
-    T.aby[k] = A.by;
-    const float dy = (float)(y & (kCell - 1));
-#pragma unroll
-    for (int e = 0; e < kRun; ++e) {
-      const int x = c.xr + e;
-      const float dx = (float)((c.xr & (kCell - 1)) + e);
-      float px, py;
-      bool ok = pixel_position<SORD, TSIP>(P, A, tinv, sinv, dx, dy, px, py);
-      ok = ok && (y < G.out_h) && (x < G.out_w);
-      double dbx = 0.0, dby = 0.0;
-      bool exact = false;
-      if constexpr (INTERP == DFR_NEAREST) {
-        // a rounding decision within reach of the FP32 error: decide in FP64
-        float tx_ = px - floorf(px), ty_ = py - floorf(py);
-        if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
-          double xs, ys;
-          ok = position_f64_ct<SORD, TSIP>(P, (double)x, (double)y, xs, ys) && fabs(xs - A.bx) < 1.0e7 &&
-               fabs(ys - A.by) < 1.0e7;
-          if (ok) {
-            px = (float)(rint(xs) - (double)A.bx);
-            py = (float)(rint(ys) - (double)A.by);
-            exact = true;
-            dbx = xs;
-            dby = ys;
-          }
-        }
-      }
-      T.rx[k][e] = px;
-      T.ry[k][e] = py;
-      if (G.debug && y < G.out_h && x < G.out_w) {
-        double2 d;
-        if (!ok) {
-          d.x = __builtin_nan("");
-          d.y = d.x;
-        } else if (exact) {
-          d.x = dbx;
-          d.y = dby;
-        } else {
-          d.x = (double)A.bx + (double)px;
-          d.y = (double)A.by + (double)py;
-        }
-        reinterpret_cast<double2 *>(G.debug)[(int64_t)y * G.out_w + x] = d;
-      }
-      if (ok) {
-        int ic, jc;
-        if constexpr (INTERP == DFR_NEAREST) {
-          ic = A.bx + (int)rintf(px);
-          jc = A.by + (int)rintf(py);
-        } else {
-          ic = A.bx + (int)floorf(px);
-          jc = A.by + (int)floorf(py);
-        }
-        int ilo = ic - SLO, ihi = ic + SHI, jlo = jc - SLO, jhi = jc + SHI;
-        if (ihi >= 0 && ilo < W && jhi >= 0 && jlo < Hs) {
-          imin = min(imin, max(ilo, 0));
-          imax = max(imax, min(ihi, W - 1));
-          jmin = min(jmin, max(jlo, 0));
-          jmax = max(jmax, min(jhi, Hs - 1));
-        }
-        T.valid |= 1u << (k * kRun + e);
-      }
-    }
-  }
-  imin = wave_min(imin);
-  imax = wave_max(imax);
-  jmin = wave_min(jmin);
-  jmax = wave_max(jmax);
-  if ((threadIdx.x & 63) == 0 && imin <= imax) {
-    atomicMin(&sh.box[0], imin);
-    atomicMax(&sh.box[1], imax);
-    atomicMin(&sh.box[2], jmin);
-    atomicMax(&sh.box[3], jmax);
-  }
-  __syncthreads();
-  T.bi0 = sh.box[0];
-  T.bi1 = sh.box[1];
-  T.bj0 = sh.box[2];
-  T.bj1 = sh.box[3];
-  T.empty = T.bi0 > T.bi1;
-  if (T.empty) T.valid = 0u;  // no tap inside the source: every pixel is uncovered
-}
-
-// Phase 4: copy the box [bi0, bi1] x [bj0, bj1] of the source into LDS (row
-// stride bw) with one wave per row and consecutive lanes on consecutive
-// columns.  The caller synchronises.
-__device__ __forceinline__ void stage_box(const FramePlan &P, int bi0, int bj0, int bw, int bh,
-                                          int lp, float *__restrict__ lds) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const auto *__restrict__ s0 = global_ptr(P.src) + (int64_t)bj0 * P.pitch + bi0;
-  for (int r = wave; r < bh; r += kThreads / 64) {
-    const auto *__restrict__ sr = s0 + (int64_t)r * P.pitch;
-    float *__restrict__ lr = lds + r * lp;
-    for (int col = lane; col < bw; col += 64) lr[col] = sr[col];
-  }
-}
 
 // Output stores are streaming (non-temporal): the output is written once
 // and never read back by the kernel, so it should not evict the source
