@@ -399,10 +399,11 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
         if constexpr (INTERP != DFR_NEAREST) {
           if (!cov) continue;
           const Anchor &A = sh.anchor[T.aidx[k]];
+          // the projective intermediates of the pixel (its position is known)
           PixelGeom pg;
-          float px, py;
-          pixel_position<SORD, TSIP>(P, A, tinv, sinv, (float)((c.xr & (kCell - 1)) + e),
-                               (float)(y & (kCell - 1)), px, py, &pg);
+          float den;
+          pixel_geom<TSIP>(P, A, tinv, sinv, (float)((c.xr & (kCell - 1)) + e),
+                           (float)(y & (kCell - 1)), pg, den);
           float fa, fau, fav, fb, fbu, fbv;
           sip_f32_grad<SORD>(P.fsA, pg.us, pg.vs, fa, fau, fav);
           sip_f32_grad<SORD>(P.fsB, pg.us, pg.vs, fb, fbu, fbv);

@@ -31,13 +31,15 @@ struct PixelGeom {
   float us, vs;   // source intermediate / S_s (SIP arguments)
 };
 
-// FP32 source position of the pixel at offset (dx, dy) from its anchor,
-// relative to (A.bx, A.by).  Returns false for directions on or behind the
+// The projective part of a pixel's position from its cell's anchor: the
+// SIP-corrected target offset, the source intermediate offset and the SIP
+// arguments (everything but the source SIP itself); `den` is 1 + k.d, whose
+// sign against the anchor's tells whether the direction is in front of the
 // source tangent plane.  TSIP compiles in the target SIP.
-template <int SORD, bool TSIP>
-__device__ __forceinline__ bool pixel_position(const FramePlan &P, const Anchor &A, float tinv,
-                                               float sinv, float dx, float dy, float &rx,
-                                               float &ry, PixelGeom *geom = nullptr) {
+template <bool TSIP>
+__device__ __forceinline__ void pixel_geom(const FramePlan &P, const Anchor &A, float tinv,
+                                           float sinv, float dx, float dy, PixelGeom &g,
+                                           float &den) {
   float du = dx, dv = dy;
   if (TSIP && P.t_order > 0) {
     float us = fmaf(dx, tinv, A.tus), vs = fmaf(dy, tinv, A.tvs);
@@ -46,7 +48,7 @@ __device__ __forceinline__ bool pixel_position(const FramePlan &P, const Anchor 
   }
   float nu = fmaf(A.g1, du, A.g2 * dv);
   float nv = fmaf(A.f1, du, A.f2 * dv);
-  float den, r;
+  float r;
   if (P.series) {
     // |e| < 1e-3: 1/(1+e) = 1 - e + e^2 to a relative 1e-9
     const float e = fmaf(A.k1, du, A.k2 * dv);
@@ -56,21 +58,30 @@ __device__ __forceinline__ bool pixel_position(const FramePlan &P, const Anchor 
     den = fmaf(A.k1, du, fmaf(A.k2, dv, 1.0f));
     r = __builtin_amdgcn_rcpf(den);
   }
-  float dU = nu * r, dV = nv * r;
-  float us = fmaf(dU, sinv, A.u0s), vs = fmaf(dV, sinv, A.v0s);
-  float ax = sip_src<SORD>(P.fsA, P.s_order, us, vs);
-  float ay = sip_src<SORD>(P.fsB, P.s_order, us, vs);
-  rx = (A.c0x + dU) + ax;
-  ry = (A.c0y + dV) + ay;
-  if (geom) {
-    geom->du = du;
-    geom->dv = dv;
-    geom->r = r;
-    geom->dU = dU;
-    geom->dV = dV;
-    geom->us = us;
-    geom->vs = vs;
-  }
+  g.du = du;
+  g.dv = dv;
+  g.r = r;
+  g.dU = nu * r;
+  g.dV = nv * r;
+  g.us = fmaf(g.dU, sinv, A.u0s);
+  g.vs = fmaf(g.dV, sinv, A.v0s);
+}
+
+// FP32 source position of the pixel at offset (dx, dy) from its anchor,
+// relative to (A.bx, A.by).  Returns false for directions on or behind the
+// source tangent plane.
+template <int SORD, bool TSIP>
+__device__ __forceinline__ bool pixel_position(const FramePlan &P, const Anchor &A, float tinv,
+                                               float sinv, float dx, float dy, float &rx,
+                                               float &ry, PixelGeom *geom = nullptr) {
+  PixelGeom g;
+  float den;
+  pixel_geom<TSIP>(P, A, tinv, sinv, dx, dy, g, den);
+  float ax = sip_src<SORD>(P.fsA, P.s_order, g.us, g.vs);
+  float ay = sip_src<SORD>(P.fsB, P.s_order, g.us, g.vs);
+  rx = (A.c0x + g.dU) + ax;
+  ry = (A.c0y + g.dV) + ay;
+  if (geom) *geom = g;
   return (A.sgn * den > 0.0f) && (fabsf(rx) < 1.0e7f) && (fabsf(ry) < 1.0e7f);
 }
 
