@@ -78,3 +78,21 @@ def test_unreachable_frame_box_is_empty(dfr, small_batch):
     co, cf, _ = dfr.reproject_batch_cropped(srcs, [c.src_wcs[0], far, c.src_wcs[2]], c.tgt_wcs,
                                             SHAPE, boxes=boxes)
     assert co[1].numel() == 0 and co[2].numel() == 0
+
+
+def test_target_sip_whole_grid_boxes(dfr, small_batch):
+    """A target with SIP has no model table: every box is the whole grid,
+    and crops still equal the full batch's pixels."""
+    from synth.sipfit import draw_sip
+    c = small_batch
+    a, b = draw_sip(2, 350.0, np.random.default_rng(4))
+    tw = c.tgt_wcs.copy(a=a, b=b)
+    srcs = [torch.from_numpy(s).cuda() for s in c.src[:3]]
+    boxes = dfr.batch_boxes(srcs, c.src_wcs[:3], tw, SHAPE)
+    assert all(bx.tolist() == [0, 0, SHAPE[1], SHAPE[0]] for bx in boxes)
+    sub = np.array([[40, 60, 300, 200], [0, 0, 64, 64], [600, 690, 40, 10]], dtype=np.int32)
+    outs, fps = dfr.reproject_batch(srcs, c.src_wcs[:3], tw, SHAPE, "bicubic")
+    co, cf, _ = dfr.reproject_batch_cropped(srcs, c.src_wcs[:3], tw, SHAPE, "bicubic", boxes=sub)
+    for i, (x0, y0, w, h) in enumerate(sub):
+        assert torch.equal(co[i], outs[i][y0:y0 + h, x0:x0 + w]), i
+        assert torch.equal(cf[i], fps[i][y0:y0 + h, x0:x0 + w]), i
