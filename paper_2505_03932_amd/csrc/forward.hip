@@ -296,8 +296,18 @@ hipError_t launch_forward_f64(const FramePlan &P, const TrigPlan &T, const TileG
 
 __global__ void zero_f32_kernel(float *p, int64_t rows, int64_t cols, int64_t pitch) {
   const int64_t n = rows * cols;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (pitch == cols && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+    // contiguous and 16-byte aligned: 16-byte stores, then the tail
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const int64_t n4 = n >> 2;
+    f4v *q = reinterpret_cast<f4v *>(p);
+    for (int64_t i = t0; i < n4; i += stride) q[i] = (f4v){0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t i = (n4 << 2) + t0; i < n; i += stride) p[i] = 0.0f;
+    return;
+  }
+  for (int64_t i = t0; i < n; i += stride) {
     int64_t r = i / cols;
     p[r * pitch + (i - r * cols)] = 0.0f;
   }
