@@ -300,14 +300,15 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
       return DFR_E_DEVICE;
     if (run.reach_host) {
       // the reach boxes the prepass recorded, back to the host (no model
-      // table: every frame may reach everywhere, reported as -1)
-      if (!models) {
-        for (int i = 0; i < 4 * n; ++i) run.reach_host[i] = -1;
-      } else if (hipMemcpyAsync(run.reach_host, reach, (size_t)16 * n, hipMemcpyDeviceToHost,
-                                stream) != hipSuccess ||
-                 hipStreamSynchronize(stream) != hipSuccess) {
+      // table: every frame may reach everywhere, reported as -1); the wait
+      // also ends the frame table's copy from the pinned staging buffer,
+      // which the next batch on this stream refills
+      if (models && hipMemcpyAsync(run.reach_host, reach, (size_t)16 * n, hipMemcpyDeviceToHost,
+                                   stream) != hipSuccess)
         return DFR_E_DEVICE;
-      }
+      if (hipStreamSynchronize(stream) != hipSuccess) return DFR_E_DEVICE;
+      if (!models)
+        for (int i = 0; i < 4 * n; ++i) run.reach_host[i] = -1;
       return DFR_OK;
     }
     const hipError_t e =
