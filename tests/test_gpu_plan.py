@@ -76,3 +76,34 @@ def test_plan_errors(dfr):
         plan.execute(torch.from_numpy(c.src).cuda())
     with pytest.raises(dfr.DfrError):
         dfr.Plan(c.src.shape, c.src_wcs, c.tgt_wcs, (64, 64), precision="f64")
+
+
+def _header(w):
+    """FITS-style header mapping of a WCS (CD form, SIP terms by keyword)."""
+    h = {"CRPIX1": w.crpix[0], "CRPIX2": w.crpix[1], "CRVAL1": w.crval[0], "CRVAL2": w.crval[1],
+         "CD1_1": w.cd[0, 0], "CD1_2": w.cd[0, 1], "CD2_1": w.cd[1, 0], "CD2_2": w.cd[1, 1]}
+    for name in ("A", "B", "AP", "BP"):
+        c = getattr(w, name.lower())
+        if c is None:
+            continue
+        h[f"{name}_ORDER"] = c.shape[0] - 1
+        for p in range(c.shape[0]):
+            for q in range(c.shape[1]):
+                if c[p, q] != 0.0:
+                    h[f"{name}_{p}_{q}"] = float(c[p, q])
+    return h
+
+
+def test_calculate_reprojection_front_end(dfr):
+    """The paper's call: (data, header) source, header target, shape_out
+    defaulting to the source shape; equals reproject with the same WCS."""
+    c = configs.sip3(scale=0.05)
+    src = torch.from_numpy(c.src).cuda()
+    sh, th = _header(c.src_wcs), _header(c.tgt_wcs)
+    out, fp = dfr.calculate_reprojection((c.src, sh), th, c.out_shape, "bicubic",
+                                         return_footprint=True)
+    o2, f2 = dfr.reproject(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic")
+    assert torch.equal(out, o2) and torch.equal(f2, fp)
+    only = dfr.calculate_reprojection((c.src, sh), th, order="nearest-neighbor")
+    o3, _ = dfr.reproject(src, c.src_wcs, c.tgt_wcs, c.src.shape, "nearest")
+    assert only.shape == c.src.shape and torch.equal(only, o3)
