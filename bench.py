@@ -18,7 +18,8 @@ the FP64 and trigonometric forms, forward+backward on the 2048^2 alignment
 case, the 64-frame batch and its coadd, the +89.5 deg precision case).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras]
-                    [--no-cpu-baseline] [--calibrate-copy] [--sweep]
+                    [--extras forms,grad,pole,batch] [--no-cpu-baseline]
+                    [--calibrate-copy] [--sweep]
 
 --sweep prints, instead, one JSON line with the size sweep of the paper's
 scaling benchmark: 256^2 .. 4000x6000 x {nearest, bilinear, bicubic} x
@@ -366,6 +367,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--extras", default="forms,grad,pole,batch",
+                    help="comma-separated extras to run: forms, grad, pole, batch")
     ap.add_argument("--sweep", action="store_true",
                     help="print the size x interpolation x SIP sweep instead of the headline")
     args = ap.parse_args()
@@ -438,8 +441,12 @@ def main():
 
     forms = {}
     if not args.no_extras:
-        for fn in (lambda: extra_forms(dfr, case, args.steps), lambda: extra_grad(dfr, args.steps),
-                   lambda: extra_pole(dfr, args.steps), lambda: extra_batch(dfr, args.steps)):
+        chosen = set(args.extras.split(","))
+        extras = {"forms": lambda: extra_forms(dfr, case, args.steps),
+                  "grad": lambda: extra_grad(dfr, args.steps),
+                  "pole": lambda: extra_pole(dfr, args.steps),
+                  "batch": lambda: extra_batch(dfr, args.steps)}
+        for fn in [f for k, f in extras.items() if k in chosen]:
             try:
                 forms.update(fn())
             except Exception as e:  # an extra must not hide the headline
