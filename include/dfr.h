@@ -291,7 +291,11 @@ dfr_status dfr_cell_model(const dfr_wcs *src_wcs, const dfr_wcs *tgt_wcs, int32_
 /* Free cached per-device workspaces and graphs (the calling thread's device). */
 dfr_status dfr_release(void);
 
+/* A static, human-readable description of a status ("unknown status" for a
+ * value outside dfr_status); never NULL, owned by the library. */
 const char *dfr_strerror(dfr_status status);
+
+/* DFR_ABI_VERSION of the built library (compare with the header's). */
 int32_t dfr_abi_version(void);
 
 #ifdef __cplusplus
