@@ -58,9 +58,46 @@ def _sip_from_header(h, name):
     return c
 
 
+_LON_LAT = {"RA": "DEC", "GLON": "GLAT", "ELON": "ELAT", "SLON": "SLAT", "HLON": "HLAT"}
+
+
+def _check_axes(h):
+    """The transform is the gnomonic (TAN) one of section 3.2 with axis 1
+    the longitude, in degrees.  A header that names another projection,
+    swapped or non-celestial axes, another LONPOLE or other units is refused
+    rather than reprojected as if it were TAN; a header without CTYPEs is
+    taken as TAN."""
+    c1, c2 = h.get("CTYPE1"), h.get("CTYPE2")
+    if c1 is not None or c2 is not None:
+        if c1 is None or c2 is None:
+            raise ValueError("CTYPE1 and CTYPE2 must both be given or both be absent")
+        c1, c2 = str(c1).strip().upper(), str(c2).strip().upper()
+        t1, p1 = c1[:4].rstrip("-"), c1[4:]
+        t2, p2 = c2[:4].rstrip("-"), c2[4:]
+        for c, p in ((c1, p1), (c2, p2)):
+            if p not in ("-TAN", "-TAN-SIP"):
+                raise ValueError(f"CTYPE {c!r}: only the gnomonic projection (TAN, TAN-SIP) "
+                                 "is supported")
+        lat = _LON_LAT.get(t1)
+        if lat is None and len(t1) == 4 and t1.endswith("LN"):
+            lat = t1[:2] + "LT"
+        if lat is None or t2 != lat:
+            raise ValueError(f"CTYPE1/CTYPE2 {c1!r}/{c2!r}: axis 1 must be a celestial "
+                             "longitude and axis 2 its latitude")
+    lp = h.get("LONPOLE")
+    if lp is not None and float(lp) != 180.0:
+        raise ValueError(f"LONPOLE = {lp!r}: the transform places the celestial pole at "
+                         "native longitude 180 deg")
+    for k in ("CUNIT1", "CUNIT2"):
+        u = h.get(k)
+        if u is not None and str(u).strip().lower() not in ("deg", ""):
+            raise ValueError(f"{k} = {u!r}: world coordinates must be in degrees")
+
+
 def wcs_from_header(h) -> Wcs:
     """WCS from a FITS-style header mapping (CRPIXi, CRVALi, CDi_j or
     PCi_j x CDELTi (paper section 3.1), A/B/AP/BP_ORDER and A_p_q ...)."""
+    _check_axes(h)
     crpix = (float(h["CRPIX1"]), float(h["CRPIX2"]))
     crval = (float(h["CRVAL1"]), float(h["CRVAL2"]))
     if "CD1_1" in h:

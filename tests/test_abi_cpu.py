@@ -209,3 +209,29 @@ def test_header_front_end(L):
     assert w.cd == pytest.approx(np.array([[-1.8e-4, -2e-5], [-2e-5, 1.8e-4]]))
     assert w.a[2, 0] == 1e-6 and w.b[0, 2] == -2e-6 and w.ap.shape == (3, 3)
     assert L.dfr_check_wcs(_wcs(L, w).s, True) == 0
+
+
+@pytest.mark.parametrize("keys,ok", [
+    ({"CTYPE1": "RA---TAN", "CTYPE2": "DEC--TAN"}, True),
+    ({"CTYPE1": "RA---TAN-SIP", "CTYPE2": "DEC--TAN-SIP", "CUNIT1": "deg", "CUNIT2": "deg"}, True),
+    ({"CTYPE1": "GLON-TAN", "CTYPE2": "GLAT-TAN"}, True),
+    ({"CTYPE1": "RA---SIN", "CTYPE2": "DEC--SIN"}, False),    # another projection
+    ({"CTYPE1": "RA---TAN", "CTYPE2": "DEC--ZEA"}, False),
+    ({"CTYPE1": "DEC--TAN", "CTYPE2": "RA---TAN"}, False),    # swapped axes
+    ({"CTYPE1": "GLON-TAN", "CTYPE2": "DEC--TAN"}, False),    # mismatched pair
+    ({"CTYPE1": "RA---TAN"}, False),                          # one axis only
+    ({"CUNIT1": "rad"}, False),
+    ({"LONPOLE": 180.0, "LATPOLE": 5.0}, True),
+    ({"LONPOLE": 0.0}, False),
+])
+def test_header_axes(keys, ok):
+    """The header front end accepts only the gnomonic projection with a
+    celestial longitude/latitude pair in degrees (section 3.2)."""
+    from paper_2505_03932_amd.api import wcs_from_header
+    h = {"CRPIX1": 1.0, "CRPIX2": 1.0, "CRVAL1": 10.0, "CRVAL2": 5.0, "CD1_1": -1e-4,
+         "CD2_2": 1e-4, **keys}
+    if ok:
+        assert wcs_from_header(h).cd[0, 0] == -1e-4
+    else:
+        with pytest.raises(ValueError):
+            wcs_from_header(h)

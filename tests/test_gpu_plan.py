@@ -81,7 +81,8 @@ def test_plan_errors(dfr):
 def _header(w):
     """FITS-style header mapping of a WCS (CD form, SIP terms by keyword)."""
     h = {"CRPIX1": w.crpix[0], "CRPIX2": w.crpix[1], "CRVAL1": w.crval[0], "CRVAL2": w.crval[1],
-         "CD1_1": w.cd[0, 0], "CD1_2": w.cd[0, 1], "CD2_1": w.cd[1, 0], "CD2_2": w.cd[1, 1]}
+         "CD1_1": w.cd[0, 0], "CD1_2": w.cd[0, 1], "CD2_1": w.cd[1, 0], "CD2_2": w.cd[1, 1],
+         "CTYPE1": "RA---TAN-SIP", "CTYPE2": "DEC--TAN-SIP", "CUNIT1": "deg", "CUNIT2": "deg"}
     for name in ("A", "B", "AP", "BP"):
         c = getattr(w, name.lower())
         if c is None:
