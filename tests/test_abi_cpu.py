@@ -235,3 +235,18 @@ def test_header_axes(keys, ok):
     else:
         with pytest.raises(ValueError):
             wcs_from_header(h)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without libdfr.so the package refuses to import: no fallback path."""
+    import shutil
+    import subprocess
+    import sys
+    import paper_2505_03932_amd as pkg
+    src = os.path.dirname(pkg.__file__)
+    dst = tmp_path / "paper_2505_03932_amd"
+    shutil.copytree(src, dst, ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc"))
+    r = subprocess.run([sys.executable, "-c", "import paper_2505_03932_amd"], cwd=tmp_path,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "libdfr.so is missing" in r.stderr and "no fallback" in r.stderr
