@@ -82,7 +82,7 @@ def _configure(L):
     L.orc_n_params.restype = C.c_int64
     L.orc_grad.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.POINTER(OrcWcs),
                            C.POINTER(OrcWcs), C.c_int64, C.c_int64, C.c_int, C.c_double,
-                           C.c_void_p, C.c_void_p, C.c_void_p]
+                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_sip_eval.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double]
     L.orc_sip_eval.restype = C.c_double
     L.orc_online_cores.restype = C.c_int
@@ -218,11 +218,14 @@ def n_params(src_wcs) -> int:
     return int(lib().orc_n_params(_W(src_wcs).ref))
 
 
-def grad(src, src_wcs, tgt_wcs, out_shape, interp, grad_out, cubic_a=-0.5, want_src=True):
+def grad(src, src_wcs, tgt_wcs, out_shape, interp, grad_out, cubic_a=-0.5, want_src=True,
+         want_abs=False):
     """Gradient of a loss with dL/dout = grad_out [H_out, W_out].
 
     Returns (grad_src [H, W] float64 or None, grad_params [n_params]) with the
-    parameter order crval(2), crpix(2), cd(4), ap[(o+1)^2], bp[(o+1)^2]."""
+    parameter order crval(2), crpix(2), cd(4), ap[(o+1)^2], bp[(o+1)^2]; with
+    want_abs also (grad_src_abs or None, grad_params_abs): every entry's sum
+    of the magnitudes of its per-pixel (and per-tap) terms."""
     src = np.ascontiguousarray(src, dtype=np.float32)
     g = np.ascontiguousarray(grad_out, dtype=np.float64)
     h, w = src.shape
@@ -231,9 +234,13 @@ def grad(src, src_wcs, tgt_wcs, out_shape, interp, grad_out, cubic_a=-0.5, want_
     S, T = _W(src_wcs), _W(tgt_wcs)
     gp = np.zeros(lib().orc_n_params(S.ref))
     gs = np.zeros((h, w)) if want_src else None
+    ga = np.zeros_like(gp) if want_abs else None
+    gsa = np.zeros((h, w)) if (want_abs and want_src) else None
+    ptr = lambda a: a.ctypes.data if a is not None else None
     lib().orc_grad(src.ctypes.data, h, w, w, S.ref, T.ref, oh, ow, _interp_id(interp),
-                   float(cubic_a), g.ctypes.data, gs.ctypes.data if gs is not None else None,
-                   gp.ctypes.data)
+                   float(cubic_a), g.ctypes.data, ptr(gs), gp.ctypes.data, ptr(gsa), ptr(ga))
+    if want_abs:
+        return gs, gp, gsa, ga
     return gs, gp
 
 

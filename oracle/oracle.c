@@ -366,14 +366,22 @@ int64_t orc_n_params(const orc_wcs *sw) {
   return 8 + na + nb;
 }
 
+/* Each gradient entry is a sum of one term per output pixel (and, for the
+ * source, per tap); the *_abs outputs, when non-null, receive the sums of
+ * the terms' magnitudes: the scale against which the rounding of such a sum
+ * is measured. */
 void orc_grad(const float *src, int64_t h, int64_t w, int64_t pitch, const orc_wcs *sw,
               const orc_wcs *tw, int64_t out_h, int64_t out_w, int interp, double a,
-              const double *grad_out, double *grad_src, double *grad_params) {
+              const double *grad_out, double *grad_src, double *grad_params,
+              double *grad_src_abs, double *grad_params_abs) {
   int64_t np = orc_n_params(sw);
   int na = sw->ap_order > 0 ? (sw->ap_order + 1) * (sw->ap_order + 1) : 0;
   if (grad_src)
     for (int64_t k = 0; k < h * w; ++k) grad_src[k] = 0.0;
+  if (grad_src_abs)
+    for (int64_t k = 0; k < h * w; ++k) grad_src_abs[k] = 0.0;
   double *gp = (double *)calloc((size_t)np, sizeof(double));
+  double *ga = (double *)calloc((size_t)np, sizeof(double));
   double det = sw->cd[0] * sw->cd[3] - sw->cd[1] * sw->cd[2];
   /* CD^-1 */
   double ci00 = sw->cd[3] / det, ci01 = -sw->cd[1] / det;
@@ -420,10 +428,13 @@ void orc_grad(const float *src, int64_t h, int64_t w, int64_t pitch, const orc_w
         double du = ci00 * dxp + ci01 * dyp;
         double dv = ci10 * dxp + ci11 * dyp;
         gp[k] += gu * du + gv * dv;
+        ga[k] += fabs(gu * du + gv * dv);
       }
       /* CRPIX */
       gp[2] += gx;
       gp[3] += gy;
+      ga[2] += fabs(gx);
+      ga[3] += fabs(gy);
       /* CD_kl: d(u,v) = -CD^-1 E_kl (u,v) */
       double uv[2] = {u, v};
       double cinv_col[2][2] = {{ci00, ci10}, {ci01, ci11}}; /* column k of CD^-1 */
@@ -432,16 +443,23 @@ void orc_grad(const float *src, int64_t h, int64_t w, int64_t pitch, const orc_w
           double du = -cinv_col[k][0] * uv[l];
           double dv = -cinv_col[k][1] * uv[l];
           gp[4 + 2 * k + l] += gu * du + gv * dv;
+          ga[4 + 2 * k + l] += fabs(gu * du + gv * dv);
         }
       /* AP, BP coefficients */
       for (int p = 0; p <= sw->ap_order && sw->ap_order > 0; ++p)
         for (int q = 0; q + p <= sw->ap_order; ++q)
+        {
           gp[8 + p * (sw->ap_order + 1) + q] += gx * ipow(u, p) * ipow(v, q);
+          ga[8 + p * (sw->ap_order + 1) + q] += fabs(gx * ipow(u, p) * ipow(v, q));
+        }
       for (int p = 0; p <= sw->bp_order && sw->bp_order > 0; ++p)
         for (int q = 0; q + p <= sw->bp_order; ++q)
+        {
           gp[8 + na + p * (sw->bp_order + 1) + q] += gy * ipow(u, p) * ipow(v, q);
+          ga[8 + na + p * (sw->bp_order + 1) + q] += fabs(gy * ipow(u, p) * ipow(v, q));
+        }
       /* source image: scatter of the interpolation weights */
-      if (grad_src) {
+      if (grad_src || grad_src_abs) {
         int64_t ix[4], iy[4];
         double wx[4], wy[4], dxw[4], dyw[4];
         int nx = taps1d(xs, interp, a, ix, wx, dxw);
@@ -450,12 +468,15 @@ void orc_grad(const float *src, int64_t h, int64_t w, int64_t pitch, const orc_w
           if (iy[j] < 0 || iy[j] >= h) continue;
           for (int i = 0; i < nx; ++i) {
             if (ix[i] < 0 || ix[i] >= w) continue;
-            grad_src[iy[j] * w + ix[i]] += g * wx[i] * wy[j] / F;
+            if (grad_src) grad_src[iy[j] * w + ix[i]] += g * wx[i] * wy[j] / F;
+            if (grad_src_abs) grad_src_abs[iy[j] * w + ix[i]] += fabs(g * wx[i] * wy[j] / F);
           }
         }
       }
     }
   }
   if (grad_params) memcpy(grad_params, gp, (size_t)np * sizeof(double));
+  if (grad_params_abs) memcpy(grad_params_abs, ga, (size_t)np * sizeof(double));
   free(gp);
+  free(ga);
 }

@@ -81,11 +81,14 @@ int64_t orc_n_params(const orc_wcs *src_wcs);
  *   grad_params = dL/d(source WCS parameters) in the order of orc_n_params
  *                 (degrees for CRVAL and CD; entries of AP/BP with
  *                 p+q > order are 0).                         (nullable)
+ *   grad_src_abs, grad_params_abs: the same sums with every term replaced
+ *                 by its magnitude (nullable).
  * Pixels with F <= 0 or an invalid position contribute nothing. */
 void orc_grad(const float *src, int64_t h, int64_t w, int64_t pitch,
               const orc_wcs *src_wcs, const orc_wcs *tgt_wcs,
               int64_t out_h, int64_t out_w, int interp, double cubic_a,
-              const double *grad_out, double *grad_src, double *grad_params);
+              const double *grad_out, double *grad_src, double *grad_params,
+              double *grad_src_abs, double *grad_params_abs);
 
 /* Array forms of the two stages (xy, radec: [n][2]; valid may be NULL). */
 void orc_pix2world_n(const orc_wcs *w, const double *xy, int64_t n, double *radec);

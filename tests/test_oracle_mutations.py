@@ -49,8 +49,19 @@ MUTANTS = {
                            ""),
     "grad_crpix_axis": ("gp[2] += gx;", "gp[2] += gy;"),
     "grad_cd_sign": ("double du = -cinv_col[k][0] * uv[l];", "double du = cinv_col[k][0] * uv[l];"),
-    "grad_scatter_weight": ("grad_src[iy[j] * w + ix[i]] += g * wx[i] * wy[j] / F;",
-                            "grad_src[iy[j] * w + ix[i]] += g * wx[i] * wy[j];"),
+    "grad_scatter_weight": ("if (grad_src) grad_src[iy[j] * w + ix[i]] += g * wx[i] * wy[j] / F;",
+                            "if (grad_src) grad_src[iy[j] * w + ix[i]] += g * wx[i] * wy[j];"),
+    # the footprint-normalisation terms of d out / d position (edge pixels)
+    "grad_footprint_sign": ("double ox = (Sx - o * Fx) / F,", "double ox = (Sx + o * Fx) / F,"),
+    "grad_footprint_dropped_y": (", oy = (Sy - o * Fy) / F;", ", oy = Sy / F;"),
+    "grad_ap_monomial": ("gp[8 + p * (sw->ap_order + 1) + q] += gx * ipow(u, p) * ipow(v, q);",
+                         "gp[8 + p * (sw->ap_order + 1) + q] += gx * ipow(u, q) * ipow(v, p);"),
+    "grad_bp_axis": ("gp[8 + na + p * (sw->bp_order + 1) + q] += gy * ipow(u, p) * ipow(v, q);",
+                     "gp[8 + na + p * (sw->bp_order + 1) + q] += gx * ipow(u, p) * ipow(v, q);"),
+    "grad_crval_dz": ("dZ[1] = Y * D2R;", "dZ[1] = -Y * D2R;"),
+    "condition_scale_signed": ("as += fabs(ww * val);", "as += ww * val;"),
+    "grad_inverse_sip_jacobian": ("double gu = gx * (1.0 + apu) + gy * bpu; /* dL/du */",
+                                  "double gu = gx * (1.0 + apu) + gy * apv; /* dL/du */"),
 }
 
 
@@ -79,11 +90,17 @@ def _battery():
         ("footprint", lambda: pins.test_footprint_closed_forms(oracle)),
         ("adjoint", lambda: pins.test_adjoint_identity_source_gradient(oracle)),
         ("fd2", lambda: pins.test_parameter_gradient_vs_central_differences(oracle, 2)),
+        ("fd_edge1", lambda: pins.test_parameter_gradient_edge_band_vs_central_differences(oracle, 1)),
+        ("fd_edge2", lambda: pins.test_parameter_gradient_edge_band_vs_central_differences(oracle, 2)),
+        ("grad_abs", lambda: pins.test_gradient_abs_scales_bound_the_sums(oracle)),
+        ("fd_wide", lambda: pins.test_sky_gradient_wide_field_vs_central_differences(oracle)),
     ]
     for interp in (0, 1, 2):
         checks.append(("identity", lambda i=interp: pins.test_identity_wcs_returns_image(oracle, i)))
     for interp in (1, 2):
         checks.append(("brute8", lambda i=interp: pins.test_brute_force_8x8(oracle, i)))
+        checks.append(("cond", lambda i=interp:
+                       pins.test_condition_scale_brute_force_and_closed_form(oracle, i)))
     for interp in (0, 1):
         checks.append(("shift", lambda i=interp: pins.test_integer_crpix_shift_is_array_shift(oracle, i)))
     for tag, fn in checks:

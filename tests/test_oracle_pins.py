@@ -411,6 +411,36 @@ def test_brute_force_8x8(orc, interp):
     assert np.all(out[~cov] == 0.0)
 
 
+@pytest.mark.parametrize("interp", [1, 2])
+def test_condition_scale_brute_force_and_closed_form(orc, interp):
+    """The scale the value tolerance is measured against, sum |w v| / F:
+    brute force over every source pixel on an 8x8 source of both signs, and
+    for a constant source c the closed forms c (bilinear, weights >= 0) and
+    c (1 + t(1-t)) (1 + s(1-s)) (interior bicubic with a = -0.5, whose outer
+    weights a t (1-t)^2 and a t^2 (1-t) are <= 0)."""
+    rng = np.random.default_rng(13)
+    src = rng.normal(0, 3, (8, 8)).astype(np.float32)
+    pts = rng.uniform(-2.5, 9.5, (400, 2))
+    k = np.arange(8)
+    A = np.array([np.sum(np.abs(_kernel(px - k, interp, -0.5)[None, :] *
+                                _kernel(py - k, interp, -0.5)[:, None] * src.astype(np.float64)))
+                  for px, py in pts])
+    _, fp, cond = orc.interp_at(src, pts, interp)
+    cov = fp > 0
+    assert cov.sum() > 200 and (~cov).sum() > 10
+    assert np.abs(cond[cov] - A[cov] / fp[cov]).max() <= 1e-12 * np.abs(A[cov] / fp[cov]).max()
+    assert np.all(cond[~cov] == 0.0)
+    const = np.full((16, 16), 2.5, np.float32)
+    inner = rng.uniform(2.0, 13.0, (300, 2))
+    _, _, cc = orc.interp_at(const, inner, interp)
+    if interp == 1:
+        assert np.abs(cc - 2.5).max() <= 1e-14
+    else:
+        t = inner - np.floor(inner)
+        ref = 2.5 * (1 + t[:, 0] * (1 - t[:, 0])) * (1 + t[:, 1] * (1 - t[:, 1]))
+        assert np.abs(cc - ref).max() <= 1e-13
+
+
 def test_nearest_is_closest_pixel_ties_to_even(orc):
     rng = np.random.default_rng(4)
     src = rng.permutation(64).astype(np.float32).reshape(8, 8)
@@ -488,16 +518,11 @@ def _perturbed(wcs, name, k, h):
     return wcs.copy(**{name: arr}), arr.flat[k] - old
 
 
-@pytest.mark.parametrize("interp", [1, 2])
-def test_parameter_gradient_vs_central_differences(orc, interp):
-    """Analytic FP64 gradient vs central differences with steps of 1e-6 px
-    of induced displacement; interior mask so no tap crosses the edge."""
-    c, true_w = _small_grad_case(interp)
-    ref, _ = orc.reproject(c.src, true_w, c.tgt_wcs, c.out_shape, c.interp)
-    pos = orc.reproject(c.src, true_w, c.tgt_wcs, c.out_shape, c.interp, want_pos=True)[2]
-    h_, w_ = c.src.shape
-    mask = ((pos[..., 0] >= 3) & (pos[..., 0] <= w_ - 4) & (pos[..., 1] >= 3) & (pos[..., 1] <= h_ - 4))
-    mask = mask.astype(np.float64)
+def _check_fd(orc, c, ref, mask, only=None):
+    """Analytic FP64 gradient of L = sum mask (out - ref)^2 at c.src_wcs
+    against central differences with steps of 1e-6 px of induced
+    displacement, for every parameter (or those named in ``only``).
+    Returns the number of parameters checked."""
     out, _ = orc.reproject(c.src, c.src_wcs, c.tgt_wcs, c.out_shape, c.interp)
     g = 2.0 * mask * (out - ref)
     _, gp = orc.grad(c.src, c.src_wcs, c.tgt_wcs, c.out_shape, c.interp, g, want_src=False)
@@ -505,7 +530,10 @@ def test_parameter_gradient_vs_central_differences(orc, interp):
     s = 0.5 * max(c.src.shape)
     scale_deg = math.sqrt(abs(np.linalg.det(wcs.cd)))
     o = wcs.ap_order
+    checked = 0
     for i, (name, k) in enumerate(_param_views(wcs)):
+        if only is not None and name not in only:
+            continue
         if name == "crval":
             h = 1e-6 * scale_deg
         elif name == "crpix":
@@ -528,6 +556,96 @@ def test_parameter_gradient_vs_central_differences(orc, interp):
         # after the sky stage, where the rounding is ~1e-12 px.
         rel = 2e-5 if name == "crval" else 5e-6
         assert abs(gp[i] - fd) <= rel * abs(fd), (name, k, gp[i], fd)
+        checked += 1
+    return checked
+
+
+@pytest.mark.parametrize("interp", [1, 2])
+def test_parameter_gradient_vs_central_differences(orc, interp):
+    """Analytic FP64 gradient vs central differences with steps of 1e-6 px
+    of induced displacement; interior mask so no tap crosses the edge."""
+    c, true_w = _small_grad_case(interp)
+    ref, _ = orc.reproject(c.src, true_w, c.tgt_wcs, c.out_shape, c.interp)
+    pos = orc.reproject(c.src, true_w, c.tgt_wcs, c.out_shape, c.interp, want_pos=True)[2]
+    h_, w_ = c.src.shape
+    mask = ((pos[..., 0] >= 3) & (pos[..., 0] <= w_ - 4) & (pos[..., 1] >= 3) & (pos[..., 1] <= h_ - 4))
+    mask = mask.astype(np.float64)
+    _check_fd(orc, c, ref, mask)
+
+
+@pytest.mark.parametrize("interp", [1, 2])
+def test_parameter_gradient_edge_band_vs_central_differences(orc, interp):
+    """Analytic gradient vs central differences on the pixels whose taps
+    straddle the source edge (footprint strictly between 0 and 1 and not
+    near 0): there out = S/F moves with F, so d out / d position carries
+    the term -out dF/dposition / F of the footprint normalisation (section
+    3.1), which the interior check never sees."""
+    c, true_w = _small_grad_case(interp)
+    ref, fp_true = orc.reproject(c.src, true_w, c.tgt_wcs, c.out_shape, c.interp)
+    mask = ((fp_true > 0.05) & (np.abs(fp_true - 1.0) > 1e-6)).astype(np.float64)
+    assert mask.sum() >= 40, mask.sum()
+    o = c.src_wcs.ap_order
+    assert _check_fd(orc, c, ref, mask) >= 8 + 2 * (o + 1) * (o + 2) // 2
+
+
+def _wide_field_case():
+    """A 64 x 64 frame of 150"/px (2.7 deg across) at Dec +55, rotated 25
+    deg, with SIP order 2 and its fitted inverse of order 3; the target is
+    offset by a few pixels and rotated 24.5 deg.  Across such a field the
+    spherical terms of the sky stages are ~1e-3 of the linear ones, far above
+    the finite-difference resolution (on the 2.85"/px frames they are ~1e-6)."""
+    rng = np.random.default_rng(31)
+    h = w = 64
+    from synth.starfield import star_field
+    src = star_field(h, w, 100.0, 5.0, 12, 31, rng=rng)
+    a, b = draw_sip(2, 32.0, rng)
+    true_w = WcsParams.tan((200.0, 55.0), 150.0, 25.0, (h, w), a=a, b=b)
+    ap, bp, _ = fit_inverse_sip(a, b, 3, true_w.crpix, (h, w))
+    true_w = true_w.copy(ap=ap, bp=bp)
+    tw = WcsParams.tan((200.02, 55.01), 150.0, 24.5, (h, w), crpix_offset=(-2.1, 1.3))
+    s_deg = 150.0 / 3600.0
+    pert = true_w.copy(crval=(true_w.crval[0] + 0.3 * s_deg / math.cos(math.radians(55.0)),
+                              true_w.crval[1] - 0.2 * s_deg),
+                       crpix=(true_w.crpix[0] + 0.2, true_w.crpix[1] - 0.1),
+                       cd=true_w.cd * (1.0 + np.array([[1e-4, -2e-4], [1.5e-4, -1e-4]])))
+    return configs.Case("wide", src, pert, tw, (h, w), 1), true_w
+
+
+def test_sky_gradient_wide_field_vs_central_differences(orc):
+    """CRVAL, CRPIX and CD gradients on a wide field, where the derivatives
+    of the spherical rotation (section 3.2) weigh in."""
+    c, true_w = _wide_field_case()
+    ref, _, pos = orc.reproject(c.src, true_w, c.tgt_wcs, c.out_shape, 1, want_pos=True)
+    h, w = c.src.shape
+    mask = ((pos[..., 0] >= 1) & (pos[..., 0] <= w - 2) & (pos[..., 1] >= 1) &
+            (pos[..., 1] <= h - 2)).astype(np.float64)
+    assert _check_fd(orc, c, ref, mask, only=("crval", "crpix", "cd")) == 8
+
+
+def test_gradient_abs_scales_bound_the_sums(orc):
+    """The magnitude sums the oracle reports beside its gradient bound the
+    gradient entry by entry, equal it for a gradient of one sign per term
+    (CRPIX with g > 0 on a ramp whose slope is positive everywhere), and
+    scale linearly with g."""
+    c, _ = _small_grad_case(2)
+    rng = np.random.default_rng(11)
+    g = rng.normal(0, 1, c.out_shape)
+    gs, gp, gsa, ga = orc.grad(c.src, c.src_wcs, c.tgt_wcs, c.out_shape, 2, g, want_abs=True)
+    assert np.all(ga >= np.abs(gp) * (1 - 1e-12)) and np.all(gsa >= np.abs(gs) * (1 - 1e-12))
+    gs2, gp2, gsa2, ga2 = orc.grad(c.src, c.src_wcs, c.tgt_wcs, c.out_shape, 2, -3.0 * g,
+                                   want_abs=True)
+    assert np.allclose(ga2, 3.0 * ga, rtol=1e-13) and np.allclose(gsa2, 3.0 * gsa, rtol=1e-13)
+    # ramp source increasing in x: d out / d x > 0 on the interior, so with
+    # g = 1 on interior pixels every CRPIX1 term is positive
+    h, w = c.src.shape
+    ramp = np.tile(np.arange(w, dtype=np.float32) * 2.0 + 5.0, (h, 1))
+    pos = orc.reproject(ramp, c.src_wcs, c.tgt_wcs, c.out_shape, 1, want_pos=True)[2]
+    inner = ((pos[..., 0] >= 3) & (pos[..., 0] <= w - 4) & (pos[..., 1] >= 3) &
+             (pos[..., 1] <= h - 4)).astype(np.float64)
+    _, gp3, _, ga3 = orc.grad(ramp, c.src_wcs, c.tgt_wcs, c.out_shape, 1, inner, want_src=False,
+                              want_abs=True)
+    assert gp3[2] > 0 and abs(ga3[2] - gp3[2]) <= 1e-12 * ga3[2]
+    assert abs(gp3[2] - 2.0 * inner.sum()) <= 1e-9 * gp3[2]
 
 
 # ----------------------------------------------------------------- coadd --
