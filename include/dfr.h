@@ -75,7 +75,9 @@ typedef enum {
                             forward SIP A/B but no inverse AP/BP                     */
   DFR_E_DEVICE = 5,      /* a HIP runtime call or kernel launch failed               */
   DFR_E_NOMEM = 6,       /* device or host allocation failed                          */
-  DFR_E_ARG = 7          /* other invalid argument (option struct size, count, ...)  */
+  DFR_E_ARG = 7,         /* other invalid argument (option struct size, count, ...)  */
+  DFR_E_LIMIT = 8        /* size beyond a fixed limit of the call (the static
+                            scratch of dfr_reproject_noalloc)                        */
 } dfr_status;
 
 typedef enum {
@@ -116,6 +118,31 @@ dfr_status dfr_reproject(const float *src, int32_t src_h, int32_t src_w, int64_t
                          int32_t out_h, int32_t out_w, dfr_interp interp,
                          float *out, float *footprint, const dfr_options *opt,
                          void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as dfr_reproject, same arguments, same kernels and bit-identical
+ * results, but it allocates nothing.  The per-cell model table that
+ * dfr_reproject keeps in a per-stream workspace lives instead in a fixed
+ * device array of DFR_NOALLOC_SCRATCH_BYTES (8 MiB) that every GPU the
+ * library runs on holds until the process ends.
+ *   Limit: with the default precision (DFR_PREC_F32) and a target without
+ *   SIP the table takes 112 B per 32x32 output cell, so at most 74,898 cells
+ *   (e.g. 8192 x 8192); a larger output returns DFR_E_LIMIT before any
+ *   device work.  The other precisions use no scratch and have no limit.
+ *   Sharing: every call on one GPU uses that GPU's one array.  Calls whose
+ *   device work can overlap (different streams without ordering, several
+ *   host threads) race on it and give wrong results; calls ordered on one
+ *   stream are safe.  The array keeps the last call's table; nothing in it
+ *   needs clearing (the model prepass writes every cell it reads).
+ *   Errors: as dfr_reproject, DFR_E_LIMIT as above, DFR_E_DEVICE if the
+ *   array's device address cannot be obtained. */
+#define DFR_NOALLOC_SCRATCH_BYTES (8u << 20)
+dfr_status dfr_reproject_noalloc(const float *src, int32_t src_h, int32_t src_w,
+                                 int64_t src_pitch, const dfr_wcs *src_wcs,
+                                 const dfr_wcs *tgt_wcs, int32_t out_h, int32_t out_w,
+                                 dfr_interp interp, float *out, float *footprint,
+                                 const dfr_options *opt, void *stream);
 
 /* A reprojection geometry prepared once for many images of the same shape
  * and WCS pair (a time series on fixed pointing, repeated reprojection of

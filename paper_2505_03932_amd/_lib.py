@@ -18,10 +18,13 @@ DFR_NEAREST, DFR_BILINEAR, DFR_BICUBIC = 0, 1, 2
 DFR_PREC_F32, DFR_PREC_F64, DFR_PREC_TRIG_F64, DFR_PREC_F32_ANCHOR = 0, 1, 2, 3
 DFR_OK = 0
 STATUS_NAMES = {0: "DFR_OK", 1: "DFR_E_NULL", 2: "DFR_E_SHAPE", 3: "DFR_E_WCS",
-                4: "DFR_E_UNSUPPORTED", 5: "DFR_E_DEVICE", 6: "DFR_E_NOMEM", 7: "DFR_E_ARG"}
+                4: "DFR_E_UNSUPPORTED", 5: "DFR_E_DEVICE", 6: "DFR_E_NOMEM", 7: "DFR_E_ARG",
+                8: "DFR_E_LIMIT"}
+DFR_E_LIMIT = 8
+DFR_NOALLOC_SCRATCH_BYTES = 8 << 20
 
 EXPORTED = [
-    "dfr_options_init", "dfr_reproject", "dfr_plan_create", "dfr_plan_execute",
+    "dfr_options_init", "dfr_reproject", "dfr_reproject_noalloc", "dfr_plan_create", "dfr_plan_execute",
     "dfr_plan_destroy", "dfr_reproject_batch", "dfr_batch_boxes", "dfr_reproject_batch_cropped",
     "dfr_coadd_batch",
     "dfr_wcs_grad_size",
@@ -77,6 +80,8 @@ def _load():
     L.dfr_options_init.restype = None
     L.dfr_reproject.argtypes = [vp, i32, i32, i64, W, W, i32, i32, st, vp, vp, O, vp]
     L.dfr_reproject.restype = st
+    L.dfr_reproject_noalloc.argtypes = [vp, i32, i32, i64, W, W, i32, i32, st, vp, vp, O, vp]
+    L.dfr_reproject_noalloc.restype = st
     L.dfr_plan_create.argtypes = [i32, i32, W, W, i32, i32, st, O, vp, C.POINTER(vp)]
     L.dfr_plan_create.restype = st
     L.dfr_plan_execute.argtypes = [vp, vp, i64, vp, vp, vp]
@@ -140,6 +145,13 @@ def dfr_reproject(src, src_h, src_w, src_pitch, src_wcs, tgt_wcs, out_h, out_w, 
     return lib.dfr_reproject(src, src_h, src_w, src_pitch, C.byref(src_wcs), C.byref(tgt_wcs),
                              out_h, out_w, interp, out, footprint,
                              C.byref(opt) if opt is not None else None, stream)
+
+
+def dfr_reproject_noalloc(src, src_h, src_w, src_pitch, src_wcs, tgt_wcs, out_h, out_w, interp,
+                          out, footprint, opt, stream) -> int:
+    return lib.dfr_reproject_noalloc(src, src_h, src_w, src_pitch, C.byref(src_wcs),
+                                     C.byref(tgt_wcs), out_h, out_w, interp, out, footprint,
+                                     C.byref(opt) if opt is not None else None, stream)
 
 
 def dfr_reproject_batch(n, frames, tgt_wcs, out_h, out_w, interp, outs, footprints, opt,

@@ -21,7 +21,7 @@ LIB = os.path.join(PKG, "libdfr.so")
 ARCH = "gfx950"
 
 SOURCES = ["tiles_bilinear.hip", "tiles_bicubic.hip", "tiles_nearest.hip", "backward.hip",
-           "forward.hip", "batch.hip", "plan.cpp", "runtime.cpp", "abi.cpp"]
+           "forward.hip", "batch.hip", "scratch.hip", "plan.cpp", "runtime.cpp", "abi.cpp"]
 
 CFLAGS = [
     "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-x", "hip",

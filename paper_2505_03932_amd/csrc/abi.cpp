@@ -14,6 +14,9 @@
 #include "launch.hpp"
 #include "plan.hpp"
 #include "runtime.hpp"
+#include "scratch.hpp"
+
+static_assert(dfr::kScratchBytes == DFR_NOALLOC_SCRATCH_BYTES, "scratch size in the header");
 
 using namespace dfr;
 
@@ -226,6 +229,54 @@ dfr_status dfr_reproject(const float *src, int32_t src_h, int32_t src_w, int64_t
     make_geom(P, out_h, out_w, (int)interp, tile, o, G, ts);
     std::lock_guard<std::mutex> lk(workspace_mutex());
     if ((s = models_for(P, out_h, out_w, o, st)) != DFR_OK) return s;
+    e = launch_forward_f32(P, G, (int)interp, ts.np, st);
+  } else {
+    TrigPlan T;
+    build_trig_plan(*src_wcs, *tgt_wcs, T);
+    TileGeom G;
+    TileShape ts;
+    make_geom(P, out_h, out_w, (int)interp, kDefaultTile, o, G, ts);
+    e = launch_forward_f64(P, T, G, (int)interp, o.precision == DFR_PREC_TRIG_F64, st);
+  }
+  return e == hipSuccess ? DFR_OK : DFR_E_DEVICE;
+}
+
+dfr_status dfr_reproject_noalloc(const float *src, int32_t src_h, int32_t src_w,
+                                 int64_t src_pitch, const dfr_wcs *src_wcs,
+                                 const dfr_wcs *tgt_wcs, int32_t out_h, int32_t out_w,
+                                 dfr_interp interp, float *out, float *footprint,
+                                 const dfr_options *opt, void *stream) {
+  dfr_status s = check_single(src, src_h, src_w, src_pitch, src_wcs, tgt_wcs, out_h, out_w,
+                              (int)interp);
+  if (s != DFR_OK) return s;
+  dfr_options o;
+  if ((s = resolve_options(opt, o)) != DFR_OK) return s;
+  if (out_h == 0 || out_w == 0) return DFR_OK;
+  if (!out) return DFR_E_NULL;
+  if (src_h == 0 || src_w == 0) src = nullptr;
+  FramePlan P;
+  build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, out, footprint, P);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (is_f32(o)) {
+    TileGeom G;
+    TileShape ts;
+    int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false);
+    make_geom(P, out_h, out_w, (int)interp, tile, o, G, ts);
+    P.models = nullptr;
+    if (o.precision == DFR_PREC_F32 && P.t_order == 0) {
+      // the model table goes to the device's fixed scratch, not the
+      // stream's workspace: refuse a grid whose table does not fit before
+      // any device call
+      const int64_t ncx = (out_w + kCell - 1) / kCell, ncy = (out_h + kCell - 1) / kCell;
+      if (ncx * ncy * (int64_t)sizeof(CellModel) > (int64_t)kScratchBytes) return DFR_E_LIMIT;
+      void *table = nullptr;
+      if (scratch_address(&table) != hipSuccess) return DFR_E_DEVICE;
+      CellModel *models = static_cast<CellModel *>(table);
+      P.models = models;
+      if (launch_cell_models(P, (int)ncx, (int)ncy, models, st) != hipSuccess)
+        return DFR_E_DEVICE;
+    }
     e = launch_forward_f32(P, G, (int)interp, ts.np, st);
   } else {
     TrigPlan T;
@@ -663,6 +714,7 @@ const char *dfr_strerror(dfr_status s) {
     case DFR_E_DEVICE: return "HIP runtime or kernel launch failure";
     case DFR_E_NOMEM: return "out of memory";
     case DFR_E_ARG: return "invalid argument";
+    case DFR_E_LIMIT: return "size beyond the fixed limit of the call (static scratch)";
   }
   return "unknown status";
 }

@@ -90,6 +90,35 @@ def test_argument_errors(L):
     assert _call(L, S, T, opt=o) == 7
 
 
+def test_noalloc_limit_and_errors(L):
+    """The allocation-free call refuses an output whose model table exceeds
+    its fixed scratch (DFR_E_LIMIT) before any device work, and reports the
+    other argument errors as dfr_reproject does."""
+    c = configs.plain(size=16)
+    S, T = _wcs(L, c.src_wcs), _wcs(L, c.tgt_wcs)
+
+    def call(out_h, out_w, opt=None, **kw):
+        a = dict(src=1, src_h=8, src_w=8, pitch=8, out=1, interp=1)
+        a.update(kw)
+        return L.dfr_reproject_noalloc(a["src"], a["src_h"], a["src_w"], a["pitch"], S.s, T.s,
+                                       out_h, out_w, a["interp"], a["out"], None, opt, None)
+
+    cells = L.DFR_NOALLOC_SCRATCH_BYTES // 112
+    assert cells == 74898
+    assert call(9000, 9000) == L.DFR_E_LIMIT  # 282 x 282 cells
+    assert call(32, 32 * (cells + 1)) == L.DFR_E_LIMIT
+    assert "limit" in L.dfr_strerror(L.DFR_E_LIMIT)
+    assert call(0, 9000) == 0
+    assert call(4, 4, pitch=7) == 2
+    assert call(4, 4, src=None) == 1
+    assert call(4, 4, out=None) == 1
+    assert call(4, 4, interp=3) == 4
+    o = L.dfr_options()
+    L.dfr_options_init(o)
+    o.size = 8
+    assert call(4, 4, opt=o) == 7
+
+
 @pytest.mark.parametrize("change,code", [
     (dict(crval=(150.0, 90.5)), 3),
     (dict(crval=(float("nan"), 2.0)), 3),
