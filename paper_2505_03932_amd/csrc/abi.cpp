@@ -46,8 +46,9 @@ dfr_status models_for(FramePlan &P, int32_t out_h, int32_t out_w, const dfr_opti
   P.models = nullptr;
   if (o.precision != DFR_PREC_F32 || P.t_order > 0) return DFR_OK;
   const int ncx = (out_w + kCell - 1) / kCell, ncy = (out_h + kCell - 1) / kCell;
-  void *buf = workspace_buffer(workspace(st), (size_t)ncx * ncy * sizeof(CellModel));
-  if (!buf) return DFR_E_NOMEM;
+  void *buf = nullptr;
+  dfr_status s = workspace_buffer(workspace(st), (size_t)ncx * ncy * sizeof(CellModel), &buf);
+  if (s != DFR_OK) return s;
   CellModel *table = static_cast<CellModel *>(buf);
   P.models = table;
   return launch_cell_models(P, ncx, ncy, table, st) == hipSuccess ? DFR_OK : DFR_E_DEVICE;
@@ -550,8 +551,9 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
   std::lock_guard<std::mutex> lk(workspace_mutex());
   Workspace *w = workspace(st);
   size_t bytes = ((size_t)std::max(G.n_tiles, 1) * ns + ns) * sizeof(double);
-  double *part = static_cast<double *>(workspace_buffer(w, bytes));
-  if (!part) return DFR_E_NOMEM;
+  void *buf = nullptr;
+  if ((s = workspace_buffer(w, bytes, &buf)) != DFR_OK) return s;
+  double *part = static_cast<double *>(buf);
   double *totals = part + (size_t)std::max(G.n_tiles, 1) * ns;
   if (G.n_tiles > 0 &&
       launch_backward(P, G, (int)interp, ts.np, grad_out, grad_src, src_w, part, st) != hipSuccess)
@@ -569,8 +571,10 @@ dfr_status dfr_sq_residual(const float *out, const float *ref, const float *mask
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
   std::lock_guard<std::mutex> lk(workspace_mutex());
-  double *part = static_cast<double *>(workspace_buffer(workspace(st), blocks * sizeof(double)));
-  if (!part) return DFR_E_NOMEM;
+  void *buf = nullptr;
+  dfr_status s = workspace_buffer(workspace(st), blocks * sizeof(double), &buf);
+  if (s != DFR_OK) return s;
+  double *part = static_cast<double *>(buf);
   return launch_sq_residual(out, ref, mask, n, part, blocks, loss, grad_out, st) == hipSuccess
              ? DFR_OK
              : DFR_E_DEVICE;

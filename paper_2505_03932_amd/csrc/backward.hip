@@ -259,6 +259,21 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
     if (!(F > 0.0f)) return false;
     float iF = all_in ? 1.0f : __builtin_amdgcn_rcpf(F);
     float c = g * iF;
+    // Where taps leave the source, d out = (dS - out dF) / F cancels the
+    // level of the values; taking every value relative to one in-bounds tap
+    // (exact: the in-bounds taps form a product set, so both dS and out dF
+    // move by vr dF) leaves a rounding relative to the local contrast
+    // instead.  Interior pixels use vr = 0.
+    float vr = 0.0f;
+    if (!all_in) {
+      int kr = 0, lr = 0;
+#pragma unroll
+      for (int k = NT - 1; k >= 0; --k) {
+        if (inx[k]) kr = k;
+        if (iny[k]) lr = k;
+      }
+      vr = fetch(i0 + kr, j0 + lr);  // F > 0: some tap is in bounds on each axis
+    }
     float S = 0.0f, Sx = 0.0f, Sy = 0.0f;
 #pragma unroll
     for (int l = 0; l < NT; ++l) {
@@ -266,7 +281,7 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
 #pragma unroll
       for (int k = 0; k < NT; ++k) {
         if (inx[k] && iny[l]) {
-          float v = fetch(i0 + k, j0 + l);
+          float v = fetch(i0 + k, j0 + l) - vr;
           row = fmaf(wx[k], v, row);
           rowd = fmaf(dx[k], v, rowd);
           scatter(k, l, i0 + k, j0 + l, c * wx[k] * wy[l]);

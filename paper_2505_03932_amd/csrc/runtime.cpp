@@ -181,12 +181,17 @@ Workspace *workspace(hipStream_t stream) {
   return &w;
 }
 
-void *workspace_buffer(Workspace *w, size_t bytes) {
-  if (!w) return nullptr;
-  if (w->cap >= bytes && w->buf) return w->buf;
+dfr_status workspace_buffer(Workspace *w, size_t bytes, void **buf) {
+  *buf = nullptr;
+  if (!w) return DFR_E_DEVICE;
+  if (w->cap >= bytes && w->buf) {
+    *buf = w->buf;
+    return DFR_OK;
+  }
   if (w->buf) {
-    // work already queued on this stream may still use the old buffer
-    if (hipStreamSynchronize(w->stream) != hipSuccess) return nullptr;
+    // work already queued on this stream may still use the old buffer; a
+    // failed wait is a device error (the old buffer is kept)
+    if (hipStreamSynchronize(w->stream) != hipSuccess) return DFR_E_DEVICE;
     (void)hipFree(w->buf);
     w->buf = nullptr;
     w->cap = 0;
@@ -194,10 +199,11 @@ void *workspace_buffer(Workspace *w, size_t bytes) {
   size_t cap = std::max<size_t>(bytes + bytes / 4, 1 << 20);
   if (hipMalloc(&w->buf, cap) != hipSuccess) {
     w->buf = nullptr;
-    return nullptr;
+    return DFR_E_NOMEM;
   }
   w->cap = cap;
-  return w->buf;
+  *buf = w->buf;
+  return DFR_OK;
 }
 
 namespace {
@@ -252,8 +258,10 @@ dfr_status run_batch(const std::vector<FramePlan> &plans, const TileGeom &G, int
   const size_t tofs = ((size_t)nzero * 4 + 255) & ~(size_t)255;
   const size_t mofs = (tofs + table + 255) & ~(size_t)255;
   const size_t mbytes = models ? (size_t)n * ncells * sizeof(CellModel) : 0;
-  char *dev = static_cast<char *>(workspace_buffer(w, mofs + mbytes));
-  if (!dev) return DFR_E_NOMEM;
+  void *wsbuf = nullptr;
+  dfr_status ws = workspace_buffer(w, mofs + mbytes, &wsbuf);
+  if (ws != DFR_OK) return ws;
+  char *dev = static_cast<char *>(wsbuf);
   int *counter = reinterpret_cast<int *>(dev);
   int32_t *reach = reinterpret_cast<int32_t *>(dev) + 4;
   FramePlan *plans_dev = reinterpret_cast<FramePlan *>(dev + tofs);

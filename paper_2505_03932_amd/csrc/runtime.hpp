@@ -61,7 +61,10 @@ struct Workspace {
 
 std::mutex &workspace_mutex();
 Workspace *workspace(hipStream_t stream);
-void *workspace_buffer(Workspace *w, size_t bytes);
+// Device scratch of at least `bytes` for the workspace, into *buf:
+// DFR_E_DEVICE if waiting for the stream's earlier work (before replacing a
+// smaller buffer) fails, DFR_E_NOMEM if the allocation fails.
+dfr_status workspace_buffer(Workspace *w, size_t bytes, void **buf);
 void release_workspaces();
 
 // What a batch run produces besides the default per-frame outputs.
