@@ -8,22 +8,30 @@ float32, inputs resident in HBM.  One step = one full forward pass over the
 frame through the C ABI: host set-up, the per-cell position-model prepass and
 the tile kernel (two launches on the caller's stream).
 
+Four buffer sets (source, output, footprint) are rotated, so the sources
+alone (4 x 96 MB) exceed the 256 MB last-level cache and every step reads its
+source from HBM.
+
 Beside it: the roofline of the dominant kernel, the tile kernel
 (algorithmic bytes per launch over its average duration, HIP events on its
 stream around launches of that kernel alone through a plan that holds the
-frame's cell models, against 8 TB/s), the same for the whole step, the HBM
-traffic the committed rocprofv3 PMC summary measured, the FP64 CPU oracle
-timed on this host, and the other forms of the path (nearest and bicubic,
-the FP64 and trigonometric forms, forward+backward on the 2048^2 alignment
-case, the 64-frame batch and its coadd, the +89.5 deg precision case).
+frame's cell models, against 8 TB/s), the same for the whole step, a
+measured device-copy bandwidth, the HBM traffic the committed rocprofv3 PMC
+summary measured, the other forms of the path (nearest and bicubic, the
+FP64 and trigonometric forms, forward+backward on the 2048^2 alignment case,
+the 64-frame batch and its coadd, the +89.5 deg precision case), a short run
+of the paper's size sweep, and the oracle leg: the FP64 CPU oracle timed on
+this host (all the cores the process may use, and one thread) and the
+position error of every form against it, in pixels.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-extras]
-                    [--extras forms,grad,pole,batch] [--no-cpu-baseline]
+                    [--extras forms,grad,pole,batch,sweep] [--no-cpu-baseline]
                     [--calibrate-copy] [--sweep]
 
 --sweep prints, instead, one JSON line with the size sweep of the paper's
 scaling benchmark: 256^2 .. 4000x6000 x {nearest, bilinear, bicubic} x
-{with, without SIP}.
+{with, without SIP}, with the given steps per point (the default line holds
+the same sweep at 5 timed steps per point).
 
 --calibrate-copy adds, after the timed steps, three plain device copies of a
 512,000,000-byte buffer, each from a source pushed out of the caches by a
@@ -81,7 +89,7 @@ def stored_profile(name: str, tag: str):
 class Frame:
     """Device buffers and prebuilt C structs for repeated launches."""
 
-    def __init__(self, dfr, src_np, sw, tw, shape, interp, n_sets=2, precision="f32", fp=True):
+    def __init__(self, dfr, src_np, sw, tw, shape, interp, n_sets=4, precision="f32", fp=True):
         import torch
         from paper_2505_03932_amd import api
         self.api = api
@@ -160,12 +168,29 @@ def touched_source_pixels(dfr, src_t, sw, tw, shape, interp):
     return int(torch.count_nonzero(gs).item())
 
 
+def cpu_threads():
+    """Threads the oracle may use here: the CPUs this process may run on,
+    capped by OMP_NUM_THREADS where the host sets it (a host shared between
+    GPUs gives each GPU's jobs a share of its cores)."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    n = aff
+    if cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n), aff, cap or None
+
+
 def cpu_baseline(case, interp):
-    """The FP64 oracle on this host's cores (at most 16 threads): whole
-    passes over the headline frame until about 12 s of CPU work (wall time
-    x threads) are done, at most 8 passes."""
+    """The FP64 oracle on this host: whole passes over the headline frame on
+    every core the process may use until about 12 s of CPU work (wall time
+    x threads) are done (at most 8 passes), then one thread on every 4th row
+    of the frame."""
     import oracle
-    threads = max(1, min(os.cpu_count() or 1, 16))
+    threads, aff, cap = cpu_threads()
+    oh, ow = case.out_shape
     rows8 = np.arange(8, dtype=np.int64)
     oracle.reproject(case.src, case.src_wcs, case.tgt_wcs, case.out_shape, interp, rows=rows8,
                      threads=threads)
@@ -178,11 +203,114 @@ def cpu_baseline(case, interp):
         dt = time.perf_counter() - t0
         if dt * threads >= 12.0 or passes >= 8:
             break
-    npx = passes * case.out_shape[0] * case.out_shape[1]
+    npx = passes * oh * ow
+    rows = np.arange(0, oh, 4, dtype=np.int64)
+    t1 = time.perf_counter()
+    oracle.reproject(case.src, case.src_wcs, case.tgt_wcs, case.out_shape, interp, rows=rows,
+                     threads=1)
+    dt1 = time.perf_counter() - t1
+    npx1 = len(rows) * ow
     return {"value": round(npx / dt / 1e6, 3), "unit": "Mpix/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{passes} whole passes over the 6000x4000 SIP frame ({npx} px, {interp}), "
-                      f"FP64, {dt:.1f} s wall on {threads} threads"}
+                      f"FP64, {dt:.1f} s wall on {threads} threads",
+            "host_cpus": os.cpu_count(), "affinity_cpus": aff, "omp_num_threads": cap,
+            "one_thread": {"value": round(npx1 / dt1 / 1e6, 3), "unit": "Mpix/s", "cores": 1,
+                           "sample": f"every 4th row of the same frame ({npx1} px), "
+                                     f"{dt1:.1f} s wall"}}
+
+
+def _pos_err(dfr, src_t, src_np, sw, tw, shape, interp, rows, precision="f32"):
+    """Max and RMS distance (px) between the source positions a GPU run
+    interpolated at (its debug output) and the oracle's FP64 positions, on
+    the target rows `rows`."""
+    import torch
+    import oracle
+    _, _, pos = dfr.reproject(src_t, sw, tw, shape, interp, precision=precision,
+                              debug_positions=True)
+    gp = pos[torch.from_numpy(rows).to(pos.device)].cpu().numpy()
+    del pos
+    _, _, op = oracle.reproject(src_np, sw, tw, shape, interp, rows=rows, want_pos=True)
+    ok = np.isfinite(gp[..., 0]) & np.isfinite(op[..., 0])
+    d = np.hypot(*(gp[ok] - op[ok]).T) if ok.any() else np.zeros(1)
+    return {"max": float(d.max()), "rms": float(np.sqrt(np.mean(d * d))),
+            "px_compared": int(ok.sum())}
+
+
+def _rows(h, n):
+    return np.unique(np.linspace(0, h - 1, n).round().astype(np.int64))
+
+
+def position_errors(dfr, case, forms):
+    """Position error against the oracle for the headline and every form in
+    `forms` (sampled rows of each workload)."""
+    import torch
+    from synth import configs
+    out = {}
+    src = torch.from_numpy(case.src).cuda()
+    rows = _rows(case.out_shape[0], 16)
+    args = (src, case.src, case.src_wcs, case.tgt_wcs, case.out_shape)
+    out["sip3_bilinear"] = _pos_err(dfr, *args, "bilinear", rows)
+    for key, interp, prec in (("sip3_nearest", "nearest", "f32"),
+                              ("sip3_bicubic", "bicubic", "f32"),
+                              ("sip3_bilinear_f32_anchor", "bilinear", "f32_anchor"),
+                              ("sip3_bilinear_f64", "bilinear", "f64"),
+                              ("sip3_bilinear_trig", "bilinear", "trig")):
+        if key in forms:
+            out[key] = _pos_err(dfr, *args, interp, rows, prec)
+    del src
+    if "grad2048_bicubic_fwd" in forms:
+        c = configs.grad()
+        s = torch.from_numpy(c.src).cuda()
+        e = _pos_err(dfr, s, c.src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic",
+                     _rows(c.out_shape[0], 16))
+        out["grad2048_bicubic_fwd"] = e
+        out["grad2048_bicubic_fwd_bwd"] = e
+    if "pole8192_bilinear_f32" in forms:
+        c = configs.pole()
+        s = torch.from_numpy(c.src).cuda()
+        for prec in ("f32", "f64"):
+            out[f"pole8192_bilinear_{prec}"] = _pos_err(dfr, s, c.src, c.src_wcs, c.tgt_wcs,
+                                                        c.out_shape, "bilinear",
+                                                        _rows(c.out_shape[0], 8), prec)
+        del s
+    if "batch64_8192_bilinear" in forms:
+        c = configs.batch()
+        worst = None
+        for i in (0, 21, 42, 63):
+            s = torch.from_numpy(c.src[i]).cuda()
+            e = _pos_err(dfr, s, c.src[i], c.src_wcs[i], c.tgt_wcs, c.out_shape, "bilinear",
+                         _rows(c.out_shape[0], 8))
+            if worst is None or e["max"] > worst["max"]:
+                worst = dict(e, frame=i)
+        for key in ("batch64_8192_bilinear", "batch64_8192_bilinear_cropped",
+                    "coadd64_8192_bilinear"):
+            out[key] = dict(worst, note="frames 0, 21, 42, 63; the largest")
+    torch.cuda.empty_cache()
+    return out
+
+
+def copy_bandwidth():
+    """A plain device-to-device copy of 1 GiB (torch copy_), best of 5, as
+    read + write bytes per second: what a streaming kernel reaches here."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 1e30
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return {"copy_gbs": round(2 * 4 * n / best / 1e6, 1), "copy_bytes": 2 * 4 * n,
+            "copy_how": "torch copy_ of a 1 GiB float32 buffer on the device, best of 5"}
 
 
 # ------------------------------------------------------------------ extras --
@@ -367,8 +495,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
-    ap.add_argument("--extras", default="forms,grad,pole,batch",
-                    help="comma-separated extras to run: forms, grad, pole, batch")
+    ap.add_argument("--extras", default="forms,grad,pole,batch,sweep",
+                    help="comma-separated extras to run: forms, grad, pole, batch, sweep")
     ap.add_argument("--sweep", action="store_true",
                     help="print the size x interpolation x SIP sweep instead of the headline")
     args = ap.parse_args()
@@ -421,12 +549,16 @@ def main():
             "step_launches": "cell_models_kernel + reproject_tiles",
             "touched_src_px": touched}
     if split:
-        # the tile kernel alone, from the committed kernel trace of this command
+        # the same launches (the plan executes) in the committed kernel trace
+        # of this measurement, and every launch of the tile kernel there
         roof["trace_tiles_us"] = split["tiles_us"]
+        roof["trace_tiles_all_launches_us"] = split.get("tiles_all_us")
         roof["trace_models_us"] = split["models_us"]
-        roof["tiles_frac_from_trace"] = round(alg_bytes / (split["tiles_us"] * 1e3) / HBM_PEAK_GBS, 4)
+        roof["frac_from_trace"] = round(alg_bytes / (split["tiles_us"] * 1e3) / HBM_PEAK_GBS, 4)
+    roof["buffer_sets"] = len(frame.sets)
     del frame
     torch.cuda.empty_cache()
+    roof.update(copy_bandwidth())
     if args.calibrate_copy:
         n = 128_000_000  # 512,000,000 bytes, twice the last-level cache
         a = torch.full((n,), 1.0, dtype=torch.float32, device="cuda")
@@ -440,6 +572,7 @@ def main():
         torch.cuda.empty_cache()
 
     forms = {}
+    sweep_rows = None
     if not args.no_extras:
         chosen = set(args.extras.split(","))
         extras = {"forms": lambda: extra_forms(dfr, case, args.steps),
@@ -452,9 +585,25 @@ def main():
             except Exception as e:  # an extra must not hide the headline
                 forms.setdefault("errors", []).append(repr(e))
             log("extras so far:", json.dumps(forms))
+        if "sweep" in chosen:
+            try:
+                sweep_rows = sweep(dfr, 5, 2)
+            except Exception as e:
+                forms.setdefault("errors", []).append(repr(e))
     cpu = None
+    pos_err = None
     if not args.no_cpu_baseline:
+        # the oracle leg: its timing on this host, and the position error of
+        # every result against it
         cpu = cpu_baseline(case, "bilinear")
+        try:
+            errs = position_errors(dfr, case, forms)
+            pos_err = errs.pop("sip3_bilinear")
+            for k, e in errs.items():
+                if k in forms:
+                    forms[k]["pos_err_px"] = e
+        except Exception as e:
+            forms.setdefault("errors", []).append(repr(e))
 
     line = {
         "metric": "output Mpix/s (bilinear/bicubic, SIP-3) + % HBM roofline; fwd+bwd Mpix/s",
@@ -464,8 +613,11 @@ def main():
         "data": "synthetic (seeded star field, SIP order 3 + fitted inverse order 4)",
         "config": {"workload": "6000x4000 SIP-3 frame -> 6000x4000 TAN target, bilinear, "
                                "out+footprint f32", "out_px": npx},
-        "roofline": roof, "cpu_baseline": cpu, "forms": forms,
+        "roofline": roof, "cpu_baseline": cpu, "pos_err_px": pos_err, "forms": forms,
     }
+    if sweep_rows is not None:
+        line["sweep"] = {"steps": 5, "warmup": 2, "note": "whole forward step per point",
+                         "rows": sweep_rows}
     print(json.dumps(line), flush=True)
 
 
