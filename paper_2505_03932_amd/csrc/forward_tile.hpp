@@ -110,6 +110,15 @@ __device__ __forceinline__ bool tile_out_of_reach(const FramePlan &P, const Tile
 // accumulators (the coadd), so the per-pixel arithmetic is the same code
 // either way.
 struct StoreSink {
+  // nearest: pixels whose rounding is decided in FP64 are stored first with
+  // the FP32 decision and overwritten by pixel() after the gather
+  static constexpr bool kDeferTies = true;
+  __device__ __forceinline__ void pixel(const FramePlan &P, const TileGeom &G, int y, int x,
+                                        float o, float f) {
+    const int64_t off = (int64_t)y * G.out_w + x;
+    __builtin_nontemporal_store(o, global_ptr(P.out) + off);
+    if (P.fp) __builtin_nontemporal_store(f, global_ptr(P.fp) + off);
+  }
   template <int NP>
   __device__ __forceinline__ void uncovered(const FramePlan &P, const TileGeom &G, int tile) {
     tile_uncovered<NP>(P, G, tile);
@@ -127,6 +136,7 @@ struct StoreSink {
 
 template <int NP>
 struct StackSink {
+  static constexpr bool kDeferTies = false;  // sums cannot be corrected afterwards
   float s[NP][kRun];  // sum of out * F
   float w[NP][kRun];  // sum of F
   template <int NP_>
@@ -150,6 +160,15 @@ struct StackSink {
 // [crop h][crop w] arrays of the target pixels x0 .. x0+w-1, y0 .. y0+h-1;
 // pixels of the tile outside the window are not stored.
 struct CropSink {
+  static constexpr bool kDeferTies = true;
+  __device__ __forceinline__ void pixel(const FramePlan &P, const TileGeom &G, int y, int x,
+                                        float o, float f) {
+    const int cx = P.crop[0], cy = P.crop[1], cw = P.crop[2], ch = P.crop[3];
+    if (y < cy || y >= cy + ch || x < cx || x >= cx + cw) return;
+    const int64_t off = (int64_t)(y - cy) * cw + (x - cx);
+    __builtin_nontemporal_store(o, global_ptr(P.out) + off);
+    if (P.fp) __builtin_nontemporal_store(f, global_ptr(P.fp) + off);
+  }
   template <int NP>
   __device__ __forceinline__ void uncovered(const FramePlan &P, const TileGeom &G, int tile);
   __device__ __forceinline__ void row(const FramePlan &P, const TileGeom &G, int, int y, int xr,
@@ -351,10 +370,15 @@ struct FwdPos {
   float rx[NP][kRun], ry[NP][kRun];
   int abx[NP], aby[NP];  // cell base position minus the box origin, per run
   unsigned valid;        // bit k * kRun + e: pixel (k, e) has a position
+  unsigned tie;          // nearest, deferred: pixel (k, e) needs the FP64 decision
 };
 
 // Phase 3: every pixel's position from its cell's model or anchor (sh.cell).
-template <int INTERP, int SORD, int NP>
+// Nearest: a pixel whose FP32 position lies within 1e-4 px of a rounding
+// tie is decided from its FP64 position, here (DEFER false) or after the
+// gather by nearest_ties (DEFER true: only a bit is kept here, so the FP64
+// chain's registers are not live across the tile's main work).
+template <int INTERP, int SORD, int NP, bool DEFER>
 __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeom &G,
                                                const TileXY &T, const FwdShared &sh,
                                                const TileBox &B, FwdPos<NP> &R) {
@@ -363,6 +387,7 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
   const float hc = (float)kHalfCell;
   const int xr = T.xr;
   R.valid = 0u;
+  R.tie = 0u;
   if (B.all_model && B.interior && !G.debug) {
     // certified cubic models throughout, tile inside the output: every pixel
     // is valid
@@ -383,8 +408,12 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
           // a rounding decision within reach of the FP32 error: decide in FP64
           float tx_ = px - floorf(px), ty_ = py - floorf(py);
           if (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f) {
-            double xs, ys;
-            nearest_exact<SORD, TSIP>(P, xr + e, y, M.bx, M.by, px, py, xs, ys);
+            if constexpr (DEFER) {
+              R.tie |= 1u << (k * kRun + e);
+            } else {
+              double xs, ys;
+              nearest_exact<SORD, TSIP>(P, xr + e, y, M.bx, M.by, px, py, xs, ys);
+            }
           }
         }
         R.rx[k][e] = px;
@@ -426,8 +455,12 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
           // a rounding decision within reach of the FP32 error: decide in FP64
           float tx_ = px - floorf(px), ty_ = py - floorf(py);
           if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
-            ok = nearest_exact<SORD, TSIP>(P, x, y, bx, by, px, py, dbx, dby);
-            exact = ok;
+            if constexpr (DEFER) {
+              R.tie |= 1u << (k * kRun + e);
+            } else {
+              ok = nearest_exact<SORD, TSIP>(P, x, y, bx, by, px, py, dbx, dby);
+              exact = ok;
+            }
           }
         }
         R.rx[k][e] = px;
@@ -539,10 +572,50 @@ __device__ __forceinline__ void CropSink::uncovered(const FramePlan &P, const Ti
   for (int k = 0; k < NP; ++k) row(P, G, k, T.y0 + T.ty + k * T.RP, T.xr, false, false, zo, zf);
 }
 
+// Nearest, after the gather: the pixels flagged in `tie` (bit k * kRun + e
+// for pixel e of run k) take their FP64 position, are rounded from it and
+// stored again, with the position for the debug output.  The wave first
+// waits for its earlier stores, so the correction is the last write to
+// those addresses.  The source value is read from global memory (these
+// pixels are rare).  It runs at the end of the tile, where little else is
+// live, so the FP64 chain adds no registers to the tile's main work.
+template <int SORD, int NP, class Sink>
+__device__ __forceinline__ void nearest_ties(const FramePlan &P, const TileGeom &G,
+                                             const TileXY &T, const FwdShared &sh, unsigned tie,
+                                             Sink &sink) {
+  constexpr bool TSIP = SORD == kRtOrder;
+  const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
+  __builtin_amdgcn_s_waitcnt(0);
+  while (tie) {
+    const int bit = __builtin_ctz(tie);
+    tie &= tie - 1u;
+    const int k = bit / kRun, e = bit % kRun;
+    const int y = T.y0 + T.ty + k * T.RP, x = T.xr + e;
+    const int ci = ((y >> kCellLog2) - T.cy0) * T.ncx + ((T.xr >> kCellLog2) - T.cx0);
+    const bool mk = sh.kind[ci] != 0;
+    const int bx = mk ? sh.cell[ci].model.bx : sh.cell[ci].anchor.bx;
+    const int by = mk ? sh.cell[ci].model.by : sh.cell[ci].anchor.by;
+    float px = 0.0f, py = 0.0f;
+    double xs = 0.0, ys = 0.0;
+    const bool ok = nearest_exact<SORD, TSIP>(P, x, y, bx, by, px, py, xs, ys);
+    float o = miss, f = 0.0f;
+    if (ok) {
+      const int i = bx + (int)px, j = by + (int)py;
+      if ((unsigned)i < (unsigned)P.src_w && (unsigned)j < (unsigned)P.src_h) {
+        o = global_ptr(P.src)[(int64_t)j * P.pitch + i];
+        f = 1.0f;
+      }
+    }
+    if (G.debug) debug_position(G, x, y, ok, true, xs, ys, bx, by, px, py);
+    sink.pixel(P, G, y, x, o, f);
+  }
+}
+
 // One tile of one frame: the four phases in order.
 template <int INTERP, int SORD, int NP, class Sink>
 __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom &G, int tile,
                                              float *__restrict__ lds, FwdShared &sh, Sink &sink) {
+  constexpr bool kDefer = INTERP == DFR_NEAREST && Sink::kDeferTies;
   const TileXY T = tile_xy<NP>(G, tile);
   if ((threadIdx.x >> 6) == 0) tile_cells<INTERP, SORD, NP>(P, G, T, sh);
   __syncthreads();
@@ -553,10 +626,13 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   const TileBox B = tile_box<NP>(P, G, T, sh, G.lds_cap);
   if (B.use_lds) dma_box(P, B.bi0, B.bj0, B.bw, B.bh, B.lp, lds);
   FwdPos<NP> R;
-  tile_positions<INTERP, SORD, NP>(P, G, T, sh, B, R);
+  tile_positions<INTERP, SORD, NP, kDefer>(P, G, T, sh, B, R);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   tile_gather<INTERP, NP>(P, G, T, B, lds, R, sink);
+  if constexpr (kDefer) {
+    if (R.tie) nearest_ties<SORD, NP>(P, G, T, sh, R.tie, sink);
+  }
 }
 
 }  // namespace dfr

@@ -11,7 +11,7 @@ namespace dfr {
 
 template <int INTERP, int SORD, int NP>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(NP >= 4 ? 4 : (INTERP == DFR_BILINEAR ? 8 : 6))))
+__attribute__((amdgpu_waves_per_eu(NP >= 4 ? 4 : (INTERP == DFR_BICUBIC ? 6 : 8))))
 void reproject_tiles(FramePlan P, TileGeom G) {
   extern __shared__ float lds[];
   __shared__ FwdShared sh;
