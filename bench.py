@@ -266,6 +266,7 @@ def position_errors(dfr, case, forms):
                      _rows(c.out_shape[0], 16))
         out["grad2048_bicubic_fwd"] = e
         out["grad2048_bicubic_fwd_bwd"] = e
+        out["grad2048_bicubic_fwd_bwd_deterministic"] = e
     if "pole8192_bilinear_f32" in forms:
         c = configs.pole()
         s = torch.from_numpy(c.src).cuda()
@@ -357,11 +358,20 @@ def extra_grad(dfr, steps):
         loss, g = dfr.sq_residual(out, ref)
         dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic", g)
 
+    def step_det():
+        out = fwd()
+        loss, g = dfr.sq_residual(out, ref)
+        dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic", g,
+                               deterministic=True)
+
     ms_f, _ = time_steps(fwd, steps, 2)
     ms_fb, _ = time_steps(step, steps, 2)
+    ms_fbd, _ = time_steps(step_det, steps, 2)
     return {"grad2048_bicubic_fwd": {"mpix_s": round(n / ms_f / 1e3, 1), "ms": round(ms_f, 4)},
             "grad2048_bicubic_fwd_bwd": {"mpix_s": round(n / ms_fb / 1e3, 1),
-                                         "ms": round(ms_fb, 4)}}
+                                         "ms": round(ms_fb, 4)},
+            "grad2048_bicubic_fwd_bwd_deterministic": {"mpix_s": round(n / ms_fbd / 1e3, 1),
+                                                       "ms": round(ms_fbd, 4)}}
 
 
 def extra_batch(dfr, steps):

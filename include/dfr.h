@@ -51,7 +51,7 @@ extern "C" {
 #endif
 
 #define DFR_MAX_SIP_ORDER 9
-#define DFR_ABI_VERSION 1
+#define DFR_ABI_VERSION 2
 
 typedef struct dfr_wcs {
   double crpix[2];       /* CRPIX1, CRPIX2 (1-based)                              */
@@ -101,6 +101,16 @@ typedef struct dfr_options {
    * position each pixel was interpolated at (exactly the value the kernel
    * used; NaN where the direction has no source position).  For tests.     */
   double *debug_positions;
+  /* dfr_reproject_backward only: nonzero makes grad_src bitwise reproducible
+   * across runs and tile shapes.  Every contribution g w / F is rounded to a
+   * multiple of 2^-Q, 2^-Q = 2^-40 max|g| rounded down to a power of two,
+   * and the multiples are summed exactly in 64-bit integers (so no order or
+   * grouping of the additions matters); |g w / F| beyond 2^22 max|g|
+   * saturates.  Slower than the default, whose float atomics make grad_src
+   * order-dependent at the rounding level.  The WCS gradient is
+   * deterministic in both modes. */
+  int32_t deterministic;
+  int32_t reserved_;      /* must be 0 */
 } dfr_options;
 
 /* Fill `opt` with the defaults (FP32 path, a = -0.5, zeros outside, auto tile). */

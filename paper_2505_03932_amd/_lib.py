@@ -44,7 +44,8 @@ class dfr_wcs(C.Structure):
 class dfr_options(C.Structure):
     _fields_ = [("size", C.c_uint32), ("precision", C.c_int32), ("cubic_a", C.c_double),
                 ("nan_outside", C.c_int32), ("tile", C.c_int32),
-                ("debug_positions", C.c_void_p)]
+                ("debug_positions", C.c_void_p), ("deterministic", C.c_int32),
+                ("reserved_", C.c_int32)]
 
 
 class dfr_frame(C.Structure):

@@ -140,7 +140,8 @@ class CWcs:
         self.s = s
 
 
-def _opts(precision="f32", cubic_a=-0.5, nan_outside=False, tile=0, debug=None):
+def _opts(precision="f32", cubic_a=-0.5, nan_outside=False, tile=0, debug=None,
+          deterministic=False):
     o = _lib.dfr_options()
     _lib.dfr_options_init(o)
     o.precision = PRECISIONS[precision]
@@ -148,6 +149,7 @@ def _opts(precision="f32", cubic_a=-0.5, nan_outside=False, tile=0, debug=None):
     o.nan_outside = 1 if nan_outside else 0
     o.tile = int(tile)
     o.debug_positions = debug
+    o.deterministic = 1 if deterministic else 0
     return o
 
 
@@ -450,8 +452,10 @@ def wcs_with_params(template, theta) -> Wcs:
 
 
 def reproject_backward(src, src_wcs, tgt_wcs, shape_out, order, grad_out, *, want_src=True,
-                       want_wcs=True, cubic_a=-0.5, tile=0):
-    """(grad_src float32 [H, W] or None, grad_wcs float64 [n] or None)."""
+                       want_wcs=True, cubic_a=-0.5, tile=0, deterministic=False):
+    """(grad_src float32 [H, W] or None, grad_wcs float64 [n] or None).
+    deterministic=True: grad_src bitwise reproducible across runs and tile
+    shapes (exact integer sums of contributions on a fixed grid)."""
     src = _src_tensor(src)
     oh, ow = int(shape_out[0]), int(shape_out[1])
     sw, tw = CWcs(src_wcs), CWcs(tgt_wcs)
@@ -461,7 +465,8 @@ def reproject_backward(src, src_wcs, tgt_wcs, shape_out, order, grad_out, *, wan
     g = grad_out.contiguous().float()
     s = _lib.dfr_reproject_backward(src.data_ptr(), src.shape[0], src.shape[1], src.stride(0),
                                     sw.s, tw.s, oh, ow, ORDERS[order], g.data_ptr(), _ptr(gs),
-                                    _ptr(gw), _opts("f32", cubic_a, tile=tile),
+                                    _ptr(gw), _opts("f32", cubic_a, tile=tile,
+                                                    deterministic=deterministic),
                                     _stream(src.device))
     _check(s, "dfr_reproject_backward")
     return gs, gw

@@ -30,6 +30,7 @@ dfr_status resolve_options(const dfr_options *opt, dfr_options &o) {
   if (o.precision < DFR_PREC_F32 || o.precision > DFR_PREC_F32_ANCHOR) return DFR_E_UNSUPPORTED;
   if (!std::isfinite(o.cubic_a)) return DFR_E_ARG;
   if (o.tile < 0 || o.tile > kTileCount) return DFR_E_ARG;
+  if (o.reserved_ != 0) return DFR_E_ARG;
   return DFR_OK;
 }
 
@@ -205,6 +206,8 @@ void dfr_options_init(dfr_options *opt) {
   opt->nan_outside = 0;
   opt->tile = 0;
   opt->debug_positions = nullptr;
+  opt->deterministic = 0;
+  opt->reserved_ = 0;
 }
 
 dfr_status dfr_reproject(const float *src, int32_t src_h, int32_t src_w, int64_t src_pitch,
@@ -527,7 +530,8 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
   if ((int64_t)out_h * out_w > 0 && !grad_out) return DFR_E_NULL;
   if (src_h == 0 || src_w == 0) src = nullptr;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (grad_src && src_h > 0 && src_w > 0 &&
+  const bool det = o.deterministic != 0 && grad_src && src_h > 0 && src_w > 0;
+  if (grad_src && src_h > 0 && src_w > 0 && !det &&
       launch_zero_f32(grad_src, src_h, src_w, src_w, st) != hipSuccess)
     return DFR_E_DEVICE;
   FramePlan P;
@@ -537,26 +541,47 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
   TileShape ts;
   std::memset(&G, 0, sizeof(G));
   if (out_h > 0 && out_w > 0) {
-    int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false, 2,
+    // LDS: the source box and its accumulation copy (floats, or 64-bit
+    // integers in the deterministic mode)
+    const int lds_factor = det ? 3 : 2;
+    int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false, lds_factor,
                            backward_default_tile((int)interp, grad_src != nullptr));
     TileShape t4;
     // the backward kernel runs 1 or 2 rows per thread: 4-row tiles use
     // their 2-row sibling of the same width
     if (tile_shape(tile, t4) && t4.np == 4) tile -= 1;
-    make_geom(P, out_h, out_w, (int)interp, tile, o, G, ts, 2);
+    make_geom(P, out_h, out_w, (int)interp, tile, o, G, ts, lds_factor);
   }
   const int ns = backward_sums(P.s_order);
   WcsJacobian J;
   h_jacobian(*src_wcs, *tgt_wcs, J.dh);
   std::lock_guard<std::mutex> lk(workspace_mutex());
   Workspace *w = workspace(st);
-  size_t bytes = ((size_t)std::max(G.n_tiles, 1) * ns + ns) * sizeof(double);
+  // workspace: per-tile FP64 partials and their totals; in the deterministic
+  // mode also max|g| (as float bits) and the 64-bit integer sums of grad_src
+  const size_t pbytes = ((size_t)std::max(G.n_tiles, 1) * ns + ns) * sizeof(double);
+  const size_t qofs = (pbytes + 255) & ~(size_t)255;
+  const size_t bytes = det ? qofs + 256 + (size_t)src_h * src_w * sizeof(uint64_t) : pbytes;
   void *buf = nullptr;
   if ((s = workspace_buffer(w, bytes, &buf)) != DFR_OK) return s;
   double *part = static_cast<double *>(buf);
   double *totals = part + (size_t)std::max(G.n_tiles, 1) * ns;
+  int *gmax_bits = det ? reinterpret_cast<int *>(static_cast<char *>(buf) + qofs) : nullptr;
+  unsigned long long *qacc =
+      det ? reinterpret_cast<unsigned long long *>(static_cast<char *>(buf) + qofs + 256) : nullptr;
+  if (det) {
+    // zero max|g| and the integer sums (kernels, not memsets), then max|g|
+    if (launch_zero_i32(gmax_bits, 1, st) != hipSuccess ||
+        launch_zero_f32(reinterpret_cast<float *>(qacc), src_h, 2 * (int64_t)src_w,
+                        2 * (int64_t)src_w, st) != hipSuccess ||
+        launch_det_prepare(grad_out, (int64_t)out_h * out_w, gmax_bits, st) != hipSuccess)
+      return DFR_E_DEVICE;
+  }
   if (G.n_tiles > 0 &&
-      launch_backward(P, G, (int)interp, ts.np, grad_out, grad_src, src_w, part, st) != hipSuccess)
+      launch_backward(P, G, (int)interp, ts.np, grad_out, det ? nullptr : grad_src, src_w, part,
+                      qacc, gmax_bits, st) != hipSuccess)
+    return DFR_E_DEVICE;
+  if (det && launch_det_finish(qacc, src_h, src_w, gmax_bits, grad_src, src_w, st) != hipSuccess)
     return DFR_E_DEVICE;
   if (launch_backward_finish(part, G.n_tiles, ns, totals, J, P.s_order, src_wcs->ap_order,
                              src_wcs->bp_order, P.s_scale, grad_wcs, st) != hipSuccess)

@@ -8,7 +8,11 @@
 //                                            an LDS copy of the tile's source
 //                                            box (ds_add_f32), which is then
 //                                            flushed with one global atomic
-//                                            per touched source pixel;
+//                                            per touched source pixel (or, in
+//                                            the deterministic mode, every
+//                                            contribution is quantised to a
+//                                            fixed grid and summed exactly in
+//                                            64-bit integers);
 //   dL/dpos_p  = g_p (dS/dpos - out dF/dpos) / F
 // and through the map pos = (U, V) + SIP(U, V) + CRPIX - 1 with
 // (U, V) = (p/w, q/w), (p, q, w) = H t:
@@ -307,14 +311,35 @@ __device__ __forceinline__ int dpp_row(int v) {
   return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
 }
 
+// Deterministic source adjoint: every contribution v = g w / F is rounded to
+// a multiple of 2^-Q (Q fixed per call from max |g|: 2^-Q = 2^-40 max |g|,
+// rounded to a power of two) and the multiples are summed in 64-bit
+// integers.  Integer sums do not depend on the order or the grouping of
+// the additions, so the result is the same bits for every run and every
+// tile shape.  |v| beyond 2^22 max |g| (footprints below ~2.4e-7 at frame
+// edges) saturates at +-2^62.
+__device__ __forceinline__ double det_scale(const int *__restrict__ gmax_bits) {
+  const float m = __int_as_float(*gmax_bits);
+  return m > 0.0f ? ldexp(1.0, 40 - ilogbf(m)) : 1.0;
+}
+
+__device__ __forceinline__ unsigned long long det_quant(float v, double qs) {
+  double d = rint((double)v * qs);
+  d = fmin(fmax(d, -4611686018427387904.0), 4611686018427387904.0);
+  return (unsigned long long)(long long)d;
+}
+
 // SRC: the source gradient is wanted (gsrc non-null); without it the kernel
-// carries no scatter code at all.
+// carries no scatter code at all.  gq non-null: the deterministic mode
+// (gsrc unused; the integer sums go to gq, [src_h][src_w] dense).
 template <int INTERP, int SORD, int NP, bool TSIP, bool SRC>
 __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom G,
                                                           const float *__restrict__ gout,
                                                           float *__restrict__ gsrc,
                                                           int64_t gpitch,
-                                                          double *__restrict__ partials) {
+                                                          double *__restrict__ partials,
+                                                          unsigned long long *__restrict__ gq,
+                                                          const int *__restrict__ gmax_bits) {
   constexpr int NC = (SORD + 1) * (SORD + 2) / 2;
   constexpr int NS = 11 + 2 * NC;
   extern __shared__ float lds[];
@@ -334,13 +359,20 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
     const int bh = T.empty ? 0 : T.bj1 - T.bj0 + 1;
     const int lp = lds_pitch(bw);  // padded row stride (bank spread)
     constexpr bool want_src = SRC;
-    const bool use_lds = !T.empty && (want_src ? 2 : 1) * (int64_t)lp * bh <= (int64_t)G.lds_cap;
+    const bool det = SRC && gq != nullptr;
+    const double qs = det ? det_scale(gmax_bits) : 0.0;
+    // LDS: the staged box, then the accumulation box (floats, or 64-bit
+    // integers in the deterministic mode, 8-byte aligned)
+    const int lp_acc = det ? 2 * lp : lp;
+    const bool use_lds = !T.empty && (want_src ? (det ? 3 : 2) : 1) * (int64_t)lp * bh + 2 <=
+                                         (int64_t)G.lds_cap;
     float *vals = lds;
-    float *gacc = lds + (use_lds ? lp * bh : 0);
+    float *gacc = lds + (use_lds ? ((lp * bh + 1) & ~1) : 0);
+    unsigned long long *qacc = reinterpret_cast<unsigned long long *>(gacc);
     if (use_lds) {
       stage_box(P, T.bi0, T.bj0, bw, bh, lp, vals);
       if (want_src)
-        for (int i = tid; i < lp * bh; i += kThreads) gacc[i] = 0.0f;
+        for (int i = tid; i < lp_acc * bh; i += kThreads) gacc[i] = 0.0f;
     }
     __syncthreads();
     const int W = P.src_w, Hs = P.src_h;
@@ -348,10 +380,20 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
     auto fetch_lds = [&](int i, int j) -> float { return vals[(j - bj0) * lp + (i - bi0)]; };
     auto fetch_glb = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
     auto scat_lds = [&](int, int, int i, int j, float v) {
-      if (want_src) atomicAdd(&gacc[(j - bj0) * lp + (i - bi0)], v);
+      if (want_src) {
+        if (det)
+          atomicAdd(&qacc[(j - bj0) * lp + (i - bi0)], det_quant(v, qs));
+        else
+          atomicAdd(&gacc[(j - bj0) * lp + (i - bi0)], v);
+      }
     };
     auto scat_glb = [&](int, int, int i, int j, float v) {
-      if (want_src) atomicAdd(&gsrc[(int64_t)j * gpitch + i], v);
+      if (want_src) {
+        if (det)
+          atomicAdd(&gq[(int64_t)j * W + i], det_quant(v, qs));
+        else
+          atomicAdd(&gsrc[(int64_t)j * gpitch + i], v);
+      }
     };
     const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
     const float S_s = (float)P.s_scale;
@@ -371,7 +413,8 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
       int wi0 = 0, wj0 = 0;
       bool win = false;
       if constexpr (INTERP != DFR_NEAREST) {
-        if (use_lds && want_src && (T.valid >> (k * kRun) & ((1u << kRun) - 1)) == (1u << kRun) - 1) {
+        if (use_lds && want_src && !det &&
+            (T.valid >> (k * kRun) & ((1u << kRun) - 1)) == (1u << kRun) - 1) {
           win = true;
 #pragma unroll
           for (int e = 0; e < kRun; ++e) {
@@ -513,8 +556,13 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
       const int wave = tid >> 6, lane = tid & 63;
       for (int r = wave; r < bh; r += kThreads / 64)
         for (int col = lane; col < bw; col += 64) {
-          float v = gacc[r * lp + col];
-          if (v != 0.0f) atomicAdd(&gsrc[(int64_t)(bj0 + r) * gpitch + bi0 + col], v);
+          if (det) {
+            const unsigned long long q = qacc[r * lp + col];
+            if (q != 0ull) atomicAdd(&gq[(int64_t)(bj0 + r) * W + bi0 + col], q);
+          } else {
+            float v = gacc[r * lp + col];
+            if (v != 0.0f) atomicAdd(&gsrc[(int64_t)(bj0 + r) * gpitch + bi0 + col], v);
+          }
         }
     }
   }
@@ -533,7 +581,8 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
   }
 }
 
-using BwdKernel = void (*)(FramePlan, TileGeom, const float *, float *, int64_t, double *);
+using BwdKernel = void (*)(FramePlan, TileGeom, const float *, float *, int64_t, double *,
+                          unsigned long long *, const int *);
 
 template <int INTERP, int NP, bool TSIP, bool SRC>
 static BwdKernel bwd_sord(int sord) {
@@ -561,16 +610,59 @@ static BwdKernel bwd_pick(int np, int sord, bool tsip, bool src) {
 
 hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, int np,
                            const float *grad_out, float *grad_src, int64_t gsrc_pitch,
-                           double *partials, hipStream_t stream) {
+                           double *partials, unsigned long long *det_acc, const int *gmax_bits,
+                           hipStream_t stream) {
   if (G.n_tiles <= 0) return hipSuccess;
   const bool tsip = P.t_order > 0;
-  const bool src = grad_src != nullptr;
+  const bool src = grad_src != nullptr || det_acc != nullptr;
   BwdKernel k = interp == DFR_NEAREST    ? bwd_pick<DFR_NEAREST>(np, P.s_order, tsip, src)
                 : interp == DFR_BILINEAR ? bwd_pick<DFR_BILINEAR>(np, P.s_order, tsip, src)
                                          : bwd_pick<DFR_BICUBIC>(np, P.s_order, tsip, src);
   size_t lds = (size_t)G.lds_cap * sizeof(float);
   hipLaunchKernelGGL(k, dim3(G.n_tiles), dim3(kThreads), lds, stream, P, G, grad_out, grad_src,
-                     gsrc_pitch, partials);
+                     gsrc_pitch, partials, det_acc, gmax_bits);
+  return hipGetLastError();
+}
+
+// max |g| over the output gradient, as the bits of a non-negative float
+// (their integer order is the float order, so atomicMax gives the same
+// result in any order); *bits starts at 0.
+__global__ __launch_bounds__(256) void abs_max_kernel(const float *__restrict__ g, int64_t n,
+                                                      int *__restrict__ bits) {
+  float m = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    m = fmaxf(m, fabsf(g[i]));
+  m = wave_max_f(m);
+  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(bits, __float_as_int(m));
+}
+
+// The deterministic mode's integer sums back to float: grad_src = q 2^-Q.
+__global__ __launch_bounds__(256) void det_finish_kernel(const unsigned long long *__restrict__ q,
+                                                         int64_t h, int64_t w,
+                                                         const int *__restrict__ gmax_bits,
+                                                         float *__restrict__ gsrc,
+                                                         int64_t gpitch) {
+  const double inv = 1.0 / det_scale(gmax_bits);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < h * w; i += (int64_t)gridDim.x * 256) {
+    const int64_t r = i / w, col = i - r * w;
+    gsrc[r * gpitch + col] = (float)((double)(long long)q[i] * inv);
+  }
+}
+
+hipError_t launch_det_prepare(const float *grad_out, int64_t n, int *gmax_bits,
+                              hipStream_t stream) {
+  hipLaunchKernelGGL(abs_max_kernel, dim3((unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256))),
+                     dim3(256), 0, stream, grad_out, n, gmax_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_det_finish(const unsigned long long *q, int64_t h, int64_t w,
+                             const int *gmax_bits, float *grad_src, int64_t gpitch,
+                             hipStream_t stream) {
+  const int64_t n = h * w;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(det_finish_kernel, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)),
+                     dim3(256), 0, stream, q, h, w, gmax_bits, grad_src, gpitch);
   return hipGetLastError();
 }
 

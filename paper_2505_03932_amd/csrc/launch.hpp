@@ -82,9 +82,19 @@ struct WcsJacobian {
   double dh[54];  // dH_i / d theta_k at [k * 9 + i], theta = CRVAL1..2, CD1_1..CD2_2
 };
 
+// det_acc non-null: the deterministic source adjoint (grad_src unused here):
+// integer sums into det_acc [src_h][src_w], quantised with the scale from
+// gmax_bits (launch_det_prepare); launch_det_finish writes grad_src.
 hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, int np,
                            const float *grad_out, float *grad_src, int64_t gsrc_pitch,
-                           double *partials, hipStream_t stream);
+                           double *partials, unsigned long long *det_acc, const int *gmax_bits,
+                           hipStream_t stream);
+// max |g| into *gmax_bits (which must start at 0).
+hipError_t launch_det_prepare(const float *grad_out, int64_t n, int *gmax_bits,
+                              hipStream_t stream);
+hipError_t launch_det_finish(const unsigned long long *q, int64_t h, int64_t w,
+                             const int *gmax_bits, float *grad_src, int64_t gpitch,
+                             hipStream_t stream);
 hipError_t launch_backward_finish(const double *partials, int n_blocks, int n_sums,
                                   double *totals, const WcsJacobian &jac, int s_order,
                                   int ap_order, int bp_order, double s_scale, double *grad_wcs,

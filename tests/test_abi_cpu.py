@@ -31,16 +31,17 @@ def test_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(L.lib, n), n
     assert set(names) == set(L.EXPORTED)
-    assert L.dfr_abi_version() == 1
+    assert L.dfr_abi_version() == 2
 
 
 def test_struct_sizes_match_header(L):
-    # dfr_wcs: 8 doubles + 4 int32 + 4 pointers; dfr_options: 32 bytes on LP64
+    # dfr_wcs: 8 doubles + 4 int32 + 4 pointers; dfr_options: 40 bytes on LP64
     assert C.sizeof(L.dfr_wcs) == 8 * 8 + 4 * 4 + 4 * 8
-    assert C.sizeof(L.dfr_options) == 32
+    assert C.sizeof(L.dfr_options) == 40
     o = L.dfr_options()
     L.dfr_options_init(o)
-    assert o.size == 32 and o.precision == 0 and o.cubic_a == -0.5 and o.tile == 0
+    assert o.size == 40 and o.precision == 0 and o.cubic_a == -0.5 and o.tile == 0
+    assert o.deterministic == 0 and o.reserved_ == 0
 
 
 def test_tiles_and_helpers(L):
@@ -87,6 +88,9 @@ def test_argument_errors(L):
     assert _call(L, S, T, opt=o) == 7
     L.dfr_options_init(o)
     o.cubic_a = float("nan")
+    assert _call(L, S, T, opt=o) == 7
+    L.dfr_options_init(o)
+    o.reserved_ = 1
     assert _call(L, S, T, opt=o) == 7
 
 

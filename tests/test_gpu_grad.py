@@ -228,3 +228,55 @@ def test_gradient_descent_reduces_misalignment(dfr):
     err1 = np.hypot(w.crpix[0] - true_w.crpix[0], w.crpix[1] - true_w.crpix[1])
     print("CRPIX error", err0, "->", err1, flush=True)
     assert err1 < 0.05 * err0
+
+
+@pytest.mark.parametrize("interp", [1, 2])
+def test_deterministic_source_gradient(dfr, orc, interp):
+    """The deterministic mode: grad_src has the same bits on repeated runs
+    and for every tile shape, matches the oracle to the source-adjoint
+    tolerance, and the default (float atomics) mode to its rounding."""
+    c, _ = grad_case(300)
+    src = torch.from_numpy(c.src).cuda()
+    g = np.random.default_rng(21).normal(0, 1, c.out_shape).astype(np.float32)
+    gt = torch.from_numpy(g).cuda()
+    ref = None
+    for tile in (0, 1, 2, 4, 5, 7, 8, 10, 11):
+        for _ in range(2):
+            gs, _ = dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, INTERPS[interp],
+                                           gt, want_wcs=False, tile=tile, deterministic=True)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = gs.clone()
+            else:
+                assert torch.equal(gs, ref), tile
+    ogs, _ = orc.grad(c.src, c.src_wcs, c.tgt_wcs, c.out_shape, interp, g.astype(np.float64),
+                      want_src=True)
+    d = np.abs(ref.cpu().numpy().astype(np.float64) - ogs).max()
+    print(f"deterministic grad_src interp={interp}: max |gpu - oracle| / max|g| = "
+          f"{d / np.abs(g).max():.3e}", flush=True)
+    assert d <= SRC_TOL * np.abs(g).max()
+    gs0, _ = dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, INTERPS[interp], gt,
+                                    want_wcs=False)
+    assert torch.max(torch.abs(gs0 - ref)).item() <= 1e-5 * np.abs(g).max()
+
+
+def test_deterministic_full_size_alignment(dfr, orc):
+    """The 2048^2 bicubic alignment gradient in the deterministic mode: two
+    runs give the same bits (source and WCS gradients) and both match the
+    oracle."""
+    c, true_w = grad_case(2048)
+    src = torch.from_numpy(c.src).cuda()
+    mask = torch.from_numpy(interior_mask(orc, c, true_w).astype(np.float32)).cuda()
+    ref, _ = dfr.reproject(src, true_w, c.tgt_wcs, c.out_shape, "bicubic")
+    out, _ = dfr.reproject(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic")
+    _, g = dfr.sq_residual(out, ref, mask)
+    a = dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic", g,
+                               deterministic=True)
+    b = dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic", g,
+                               deterministic=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    gn = g.cpu().numpy().astype(np.float64)
+    ogs, ogw, _, oga = orc.grad(c.src, c.src_wcs, c.tgt_wcs, c.out_shape, 2, gn, want_abs=True)
+    _compare_wcs_grad(a[1].cpu().numpy(), ogw, oga, rel_tol=1e-4)
+    assert np.abs(a[0].cpu().numpy() - ogs).max() <= SRC_TOL * np.abs(gn).max()
