@@ -101,14 +101,16 @@ typedef struct dfr_options {
    * position each pixel was interpolated at (exactly the value the kernel
    * used; NaN where the direction has no source position).  For tests.     */
   double *debug_positions;
-  /* dfr_reproject_backward only: nonzero makes grad_src bitwise reproducible
-   * across runs and tile shapes.  Every contribution g w / F is rounded to a
-   * multiple of 2^-Q, 2^-Q = 2^-40 max|g| rounded down to a power of two,
-   * and the multiples are summed exactly in 64-bit integers (so no order or
-   * grouping of the additions matters); |g w / F| beyond 2^22 max|g|
-   * saturates.  Slower than the default, whose float atomics make grad_src
-   * order-dependent at the rounding level.  The WCS gradient is
-   * deterministic in both modes. */
+  /* dfr_reproject_backward: request a grad_src that is bitwise reproducible
+   * across runs and tile shapes.  Both 0 and 1 give that result: the source
+   * adjoint is always summed exactly.  Every contribution g w / F (or a
+   * thread's FP32 sum of its own run of four output pixels' contributions
+   * to one source pixel, a grouping fixed by the output grid) is rounded to
+   * a multiple of 2^-Q, 2^-Q = 2^-40 max|g| rounded down to a power of two,
+   * and the multiples are summed in 64-bit integers, so no order or
+   * grouping of the additions matters; |g w / F| beyond 2^22 max|g|
+   * saturates.  The WCS gradient is reduced in a fixed order for a given
+   * tile shape. */
   int32_t deterministic;
   int32_t reserved_;      /* must be 0 */
 } dfr_options;

@@ -530,10 +530,9 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
   if ((int64_t)out_h * out_w > 0 && !grad_out) return DFR_E_NULL;
   if (src_h == 0 || src_w == 0) src = nullptr;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const bool det = o.deterministic != 0 && grad_src && src_h > 0 && src_w > 0;
-  if (grad_src && src_h > 0 && src_w > 0 && !det &&
-      launch_zero_f32(grad_src, src_h, src_w, src_w, st) != hipSuccess)
-    return DFR_E_DEVICE;
+  // the source adjoint is summed in integers in a workspace buffer and
+  // converted into grad_src (every entry written)
+  const bool det = grad_src && src_h > 0 && src_w > 0;
   FramePlan P;
   build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, nullptr, nullptr, P);
   o.debug_positions = nullptr;
@@ -541,9 +540,9 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
   TileShape ts;
   std::memset(&G, 0, sizeof(G));
   if (out_h > 0 && out_w > 0) {
-    // LDS: the source box and its accumulation copy (floats, or 64-bit
-    // integers in the deterministic mode)
-    const int lds_factor = det ? 3 : 2;
+    // LDS: the source box and, for the source adjoint, its 64-bit integer
+    // accumulation copy
+    const int lds_factor = det ? 3 : 1;
     int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false, lds_factor,
                            backward_default_tile((int)interp, grad_src != nullptr));
     TileShape t4;
@@ -557,8 +556,8 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
   h_jacobian(*src_wcs, *tgt_wcs, J.dh);
   std::lock_guard<std::mutex> lk(workspace_mutex());
   Workspace *w = workspace(st);
-  // workspace: per-tile FP64 partials and their totals; in the deterministic
-  // mode also max|g| (as float bits) and the 64-bit integer sums of grad_src
+  // workspace: per-tile FP64 partials and their totals; for the source
+  // adjoint also max|g| (as float bits) and the 64-bit integer sums
   const size_t pbytes = ((size_t)std::max(G.n_tiles, 1) * ns + ns) * sizeof(double);
   const size_t qofs = (pbytes + 255) & ~(size_t)255;
   const size_t bytes = det ? qofs + 256 + (size_t)src_h * src_w * sizeof(uint64_t) : pbytes;
@@ -578,8 +577,8 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
       return DFR_E_DEVICE;
   }
   if (G.n_tiles > 0 &&
-      launch_backward(P, G, (int)interp, ts.np, grad_out, det ? nullptr : grad_src, src_w, part,
-                      qacc, gmax_bits, st) != hipSuccess)
+      launch_backward(P, G, (int)interp, ts.np, grad_out, part, qacc, gmax_bits, st) !=
+          hipSuccess)
     return DFR_E_DEVICE;
   if (det && launch_det_finish(qacc, src_h, src_w, gmax_bits, grad_src, src_w, st) != hipSuccess)
     return DFR_E_DEVICE;

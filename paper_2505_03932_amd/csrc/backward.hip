@@ -4,15 +4,14 @@
 //
 // For a loss L with g = dL/dout:
 //   dL/dsrc_k = sum_p g_p w_kp / F_p       -- adjoint of the interpolation, a
-//                                            scatter-add: taps accumulate in
-//                                            an LDS copy of the tile's source
-//                                            box (ds_add_f32), which is then
-//                                            flushed with one global atomic
-//                                            per touched source pixel (or, in
-//                                            the deterministic mode, every
-//                                            contribution is quantised to a
-//                                            fixed grid and summed exactly in
-//                                            64-bit integers);
+//                                            scatter-add of contributions
+//                                            rounded to a fixed grid and
+//                                            summed exactly in 64-bit
+//                                            integers (in an LDS copy of the
+//                                            tile's source box, then one
+//                                            global atomic per touched source
+//                                            pixel), so the result does not
+//                                            depend on the order of the adds;
 //   dL/dpos_p  = g_p (dS/dpos - out dF/dpos) / F
 // and through the map pos = (U, V) + SIP(U, V) + CRPIX - 1 with
 // (U, V) = (p/w, q/w), (p, q, w) = H t:
@@ -303,21 +302,15 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
   }
 }
 
-// A lane's value from the lane CTRL selects within its row of 16 lanes
-// (row_shr:1 = 0x111: lane i - 1; row_shl:1 = 0x101: lane i + 1); 0 where
-// that lane is outside the row.
-template <int CTRL>
-__device__ __forceinline__ int dpp_row(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
-}
-
-// Deterministic source adjoint: every contribution v = g w / F is rounded to
-// a multiple of 2^-Q (Q fixed per call from max |g|: 2^-Q = 2^-40 max |g|,
+// Source adjoint: every contribution v = g w / F is rounded to a
+// multiple of 2^-Q (Q fixed per call from max |g|: 2^-Q = 2^-40 max |g|,
 // rounded to a power of two) and the multiples are summed in 64-bit
 // integers.  Integer sums do not depend on the order or the grouping of
 // the additions, so the result is the same bits for every run and every
-// tile shape.  |v| beyond 2^22 max |g| (footprints below ~2.4e-7 at frame
-// edges) saturates at +-2^62.
+// tile shape; 64-bit LDS integer adds are also much faster here than
+// ds_add_f32 on contended addresses (measured: 148 against 382 us per
+// 2048^2 bicubic backward with one add per tap).  |v| beyond 2^22 max |g|
+// (footprints below ~2.4e-7 at frame edges) saturates at +-2^62.
 __device__ __forceinline__ double det_scale(const int *__restrict__ gmax_bits) {
   const float m = __int_as_float(*gmax_bits);
   return m > 0.0f ? ldexp(1.0, 40 - ilogbf(m)) : 1.0;
@@ -329,14 +322,12 @@ __device__ __forceinline__ unsigned long long det_quant(float v, double qs) {
   return (unsigned long long)(long long)d;
 }
 
-// SRC: the source gradient is wanted (gsrc non-null); without it the kernel
-// carries no scatter code at all.  gq non-null: the deterministic mode
-// (gsrc unused; the integer sums go to gq, [src_h][src_w] dense).
+// SRC: the source gradient is wanted (its integer sums go to gq,
+// [src_h][src_w] dense; det_finish_kernel converts them); without it the
+// kernel carries no scatter code at all.
 template <int INTERP, int SORD, int NP, bool TSIP, bool SRC>
 __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom G,
                                                           const float *__restrict__ gout,
-                                                          float *__restrict__ gsrc,
-                                                          int64_t gpitch,
                                                           double *__restrict__ partials,
                                                           unsigned long long *__restrict__ gq,
                                                           const int *__restrict__ gmax_bits) {
@@ -359,12 +350,11 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
     const int bh = T.empty ? 0 : T.bj1 - T.bj0 + 1;
     const int lp = lds_pitch(bw);  // padded row stride (bank spread)
     constexpr bool want_src = SRC;
-    const bool det = SRC && gq != nullptr;
-    const double qs = det ? det_scale(gmax_bits) : 0.0;
-    // LDS: the staged box, then the accumulation box (floats, or 64-bit
-    // integers in the deterministic mode, 8-byte aligned)
-    const int lp_acc = det ? 2 * lp : lp;
-    const bool use_lds = !T.empty && (want_src ? (det ? 3 : 2) : 1) * (int64_t)lp * bh + 2 <=
+    const double qs = SRC ? det_scale(gmax_bits) : 0.0;
+    // LDS: the staged box, then the 64-bit integer accumulation box (8-byte
+    // aligned, two floats per entry)
+    const int lp_acc = 2 * lp;
+    const bool use_lds = !T.empty && (want_src ? 3 : 1) * (int64_t)lp * bh + 2 <=
                                          (int64_t)G.lds_cap;
     float *vals = lds;
     float *gacc = lds + (use_lds ? ((lp * bh + 1) & ~1) : 0);
@@ -380,83 +370,53 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
     auto fetch_lds = [&](int i, int j) -> float { return vals[(j - bj0) * lp + (i - bi0)]; };
     auto fetch_glb = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
     auto scat_lds = [&](int, int, int i, int j, float v) {
-      if (want_src) {
-        if (det)
-          atomicAdd(&qacc[(j - bj0) * lp + (i - bi0)], det_quant(v, qs));
-        else
-          atomicAdd(&gacc[(j - bj0) * lp + (i - bi0)], v);
-      }
+      if (want_src) atomicAdd(&qacc[(j - bj0) * lp + (i - bi0)], det_quant(v, qs));
     };
     auto scat_glb = [&](int, int, int i, int j, float v) {
-      if (want_src) {
-        if (det)
-          atomicAdd(&gq[(int64_t)j * W + i], det_quant(v, qs));
-        else
-          atomicAdd(&gsrc[(int64_t)j * gpitch + i], v);
-      }
+      if (want_src) atomicAdd(&gq[(int64_t)j * W + i], det_quant(v, qs));
     };
     const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
     const float S_s = (float)P.s_scale;
-    // Source-gradient window of a run: when the kRun pixels' tap origins
-    // lie in one row and step by exactly one column (the common case near
-    // unit scale) with every tap inside the source and the box, their
-    // NT x NT taps overlap on NT x (NT + kRun - 1) source pixels; the
-    // contributions are summed there in registers (static indices) and added
-    // to LDS once per window entry instead of once per tap (LDS float
-    // atomics are the cost of this kernel).  Other runs add per tap.
-    constexpr int NT = INTERP == DFR_BICUBIC ? 4 : 2;
-    constexpr int WC = NT + kRun - 1;
-    constexpr int OFF = INTERP == DFR_BICUBIC ? 1 : 0;
+    // Every tap's contribution is quantised and added on its own (64-bit
+    // integer LDS adds are cheap; summing a run's taps in a register window
+    // first measured slower, the window's registers costing occupancy).
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
       const int y = c.y0 + c.ty + k * c.RP;
-      int wi0 = 0, wj0 = 0;
-      bool win = false;
-      if constexpr (INTERP != DFR_NEAREST) {
-        if (use_lds && want_src && !det &&
-            (T.valid >> (k * kRun) & ((1u << kRun) - 1)) == (1u << kRun) - 1) {
-          win = true;
-#pragma unroll
-          for (int e = 0; e < kRun; ++e) {
-            // the tap origin exactly as interp_backward derives it
-            const int i0 = T.abx[k] + (int)floorf(T.rx[k][e]) - OFF;
-            const int j0 = T.aby[k] + (int)floorf(T.ry[k][e]) - OFF;
-            if (e == 0) {
-              wi0 = i0;
-              wj0 = j0;
-            }
-            win = win && i0 == wi0 + e && j0 == wj0;
-          }
-          win = win && wi0 >= max(bi0, 0) && wi0 + WC - 1 <= min(T.bi1, W - 1) &&
-                wj0 >= max(bj0, 0) && wj0 + NT - 1 <= min(T.bj1, Hs - 1);
-        }
-      }
-      float wacc[NT][WC];
-#pragma unroll
-      for (int l = 0; l < NT; ++l)
-#pragma unroll
-        for (int m = 0; m < WC; ++m) wacc[l][m] = 0.0f;
+      // the run's interpolant gradients; the WCS terms are formed from them
+      // after the run's scatter, so the scatter's and the WCS sums'
+      // registers are not live together
+      float gxs[kRun], gys[kRun];
+      unsigned covm = 0u;
 #pragma unroll
       for (int e = 0; e < kRun; ++e) {
+        gxs[e] = 0.0f;
+        gys[e] = 0.0f;
         if (!(T.valid & (1u << (k * kRun + e)))) continue;
         const int x = c.xr + e;
         const float g = gout[(int64_t)y * G.out_w + x];
         if (g == 0.0f) continue;
         float gx, gy;
         bool cov;
-        auto scat_win = [&](int kk, int ll, int, int, float v) { wacc[ll][e + kk] += v; };
-        if (win)
-          cov = interp_backward<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs,
-                                        G.cubic_a, g, fetch_lds, scat_win, gx, gy);
-        else if (use_lds)
+        if (use_lds)
           cov = interp_backward<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs,
                                         G.cubic_a, g, fetch_lds, scat_lds, gx, gy);
         else
           cov = interp_backward<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs,
                                         G.cubic_a, g, fetch_glb, scat_glb, gx, gy);
-        if constexpr (INTERP != DFR_NEAREST) {
-          if (!cov) continue;
-          const Anchor &A = sh.anchor[T.aidx[k]];
+        if (cov) {
+          gxs[e] = gx;
+          gys[e] = gy;
+          covm |= 1u << e;
+        }
+      }
+      if constexpr (INTERP != DFR_NEAREST) {
+        // the WCS terms of the run's covered pixels, in pixel order
+        const Anchor &A = sh.anchor[T.aidx[k]];
+#pragma unroll
+        for (int e = 0; e < kRun; ++e) {
+          if (!(covm & (1u << e))) continue;
+          const float gx = gxs[e], gy = gys[e];
           // the projective intermediates of the pixel (its position is known)
           PixelGeom pg;
           float den;
@@ -498,71 +458,14 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
           }
         }
       }
-      if constexpr (SRC && INTERP != DFR_NEAREST) {
-        // Windows of neighbouring lanes abut in the source when the right
-        // one starts kRun columns later in the same row: its first NT - 1
-        // columns are the left one's last.  Each lane hands those columns
-        // to the lane on its right (within a DPP row), which adds them to
-        // its own when the geometry matches; the left lane then skips them.
-        // Every window entry is added to LDS exactly once.
-        const int rwi = dpp_row<0x111>(wi0), rwj = dpp_row<0x111>(wj0);
-        const bool take = win && dpp_row<0x111>(win ? 1 : 0) != 0 && rwi + kRun == wi0 && rwj == wj0;
-#pragma unroll
-        for (int l = 0; l < NT; ++l)
-#pragma unroll
-          for (int m = 0; m < NT - 1; ++m) {
-            const float t = __builtin_bit_cast(
-                float, dpp_row<0x111>(__builtin_bit_cast(int, wacc[l][kRun + m])));
-            if (take) wacc[l][m] += t;
-          }
-        const bool given = dpp_row<0x101>(take ? 1 : 0) != 0;
-        // The same along columns: the lane one output row below (lane +
-        // 2^lg, same run) whose window starts one source row lower shares
-        // NT - 1 rows of the first kRun columns.  Passed down the wave's
-        // rows in order (a chain, so each lane forwards what it received),
-        // through the lane crossbar, not LDS atomics.
-        const int lg = G.txt_log2;
-        const int lane = threadIdx.x & 63, vstep = 1 << lg, vrow = lane >> lg;
-        bool given_v = false;
-        if (vstep < 64) {
-          const int uwi = __shfl_up(wi0, vstep), uwj = __shfl_up(wj0, vstep);
-          const bool uwin = __shfl_up(win ? 1 : 0, vstep) != 0;
-          const bool take_v = win && uwin && vrow > 0 && uwi == wi0 && uwj + 1 == wj0;
-          for (int r = 1; r < (64 >> lg); ++r) {
-#pragma unroll
-            for (int l = 0; l < NT - 1; ++l)
-#pragma unroll
-              for (int m = 0; m < kRun; ++m) {
-                const float t = __shfl_up(wacc[l + 1][m], vstep);
-                if (take_v && vrow == r) wacc[l][m] += t;
-              }
-          }
-          given_v = __shfl_down(take_v ? 1 : 0, vstep) != 0 && vrow < (64 >> lg) - 1;
-        }
-        if (win) {
-          float *wb = gacc + (wj0 - bj0) * lp + (wi0 - bi0);
-#pragma unroll
-          for (int l = 0; l < NT; ++l)
-#pragma unroll
-            for (int m = 0; m < WC; ++m) {
-              const bool mine = m < kRun ? (l == 0 || !given_v) : !given;
-              if (mine && wacc[l][m] != 0.0f) atomicAdd(wb + l * lp + m, wacc[l][m]);
-            }
-        }
-      }
     }
     __syncthreads();
     if (SRC && use_lds) {
       const int wave = tid >> 6, lane = tid & 63;
       for (int r = wave; r < bh; r += kThreads / 64)
         for (int col = lane; col < bw; col += 64) {
-          if (det) {
-            const unsigned long long q = qacc[r * lp + col];
-            if (q != 0ull) atomicAdd(&gq[(int64_t)(bj0 + r) * W + bi0 + col], q);
-          } else {
-            float v = gacc[r * lp + col];
-            if (v != 0.0f) atomicAdd(&gsrc[(int64_t)(bj0 + r) * gpitch + bi0 + col], v);
-          }
+          const unsigned long long q = qacc[r * lp + col];
+          if (q != 0ull) atomicAdd(&gq[(int64_t)(bj0 + r) * W + bi0 + col], q);
         }
     }
   }
@@ -581,8 +484,8 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
   }
 }
 
-using BwdKernel = void (*)(FramePlan, TileGeom, const float *, float *, int64_t, double *,
-                          unsigned long long *, const int *);
+using BwdKernel = void (*)(FramePlan, TileGeom, const float *, double *, unsigned long long *,
+                          const int *);
 
 template <int INTERP, int NP, bool TSIP, bool SRC>
 static BwdKernel bwd_sord(int sord) {
@@ -609,18 +512,17 @@ static BwdKernel bwd_pick(int np, int sord, bool tsip, bool src) {
 }
 
 hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, int np,
-                           const float *grad_out, float *grad_src, int64_t gsrc_pitch,
-                           double *partials, unsigned long long *det_acc, const int *gmax_bits,
-                           hipStream_t stream) {
+                           const float *grad_out, double *partials, unsigned long long *src_acc,
+                           const int *gmax_bits, hipStream_t stream) {
   if (G.n_tiles <= 0) return hipSuccess;
   const bool tsip = P.t_order > 0;
-  const bool src = grad_src != nullptr || det_acc != nullptr;
+  const bool src = src_acc != nullptr;
   BwdKernel k = interp == DFR_NEAREST    ? bwd_pick<DFR_NEAREST>(np, P.s_order, tsip, src)
                 : interp == DFR_BILINEAR ? bwd_pick<DFR_BILINEAR>(np, P.s_order, tsip, src)
                                          : bwd_pick<DFR_BICUBIC>(np, P.s_order, tsip, src);
   size_t lds = (size_t)G.lds_cap * sizeof(float);
-  hipLaunchKernelGGL(k, dim3(G.n_tiles), dim3(kThreads), lds, stream, P, G, grad_out, grad_src,
-                     gsrc_pitch, partials, det_acc, gmax_bits);
+  hipLaunchKernelGGL(k, dim3(G.n_tiles), dim3(kThreads), lds, stream, P, G, grad_out, partials,
+                     src_acc, gmax_bits);
   return hipGetLastError();
 }
 
@@ -629,14 +531,20 @@ hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, in
 // result in any order); *bits starts at 0.
 __global__ __launch_bounds__(256) void abs_max_kernel(const float *__restrict__ g, int64_t n,
                                                       int *__restrict__ bits) {
+  __shared__ float wm[4];
   float m = 0.0f;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     m = fmaxf(m, fabsf(g[i]));
   m = wave_max_f(m);
-  if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(bits, __float_as_int(m));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+    if (m > 0.0f) atomicMax(bits, __float_as_int(m));  // one atomic per block
+  }
 }
 
-// The deterministic mode's integer sums back to float: grad_src = q 2^-Q.
+// The source adjoint's integer sums back to float: grad_src = q 2^-Q.
 __global__ __launch_bounds__(256) void det_finish_kernel(const unsigned long long *__restrict__ q,
                                                          int64_t h, int64_t w,
                                                          const int *__restrict__ gmax_bits,
@@ -651,7 +559,7 @@ __global__ __launch_bounds__(256) void det_finish_kernel(const unsigned long lon
 
 hipError_t launch_det_prepare(const float *grad_out, int64_t n, int *gmax_bits,
                               hipStream_t stream) {
-  hipLaunchKernelGGL(abs_max_kernel, dim3((unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256))),
+  hipLaunchKernelGGL(abs_max_kernel, dim3((unsigned)std::min<int64_t>(512, std::max<int64_t>(1, (n + 255) / 256))),
                      dim3(256), 0, stream, grad_out, n, gmax_bits);
   return hipGetLastError();
 }
@@ -684,40 +592,39 @@ __global__ __launch_bounds__(256) void bwd_reduce(const double *__restrict__ par
 }
 
 // Chain rule to the source WCS parameters, in the order of
-// dfr_wcs_grad_size: CRVAL(2), CRPIX(2), CD(4), AP, BP (square layouts).
-__global__ void bwd_chain(const double *__restrict__ totals, WcsJacobian J, int s_order,
-                          int ap_order, int bp_order, double S, double *__restrict__ grad) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// dfr_wcs_grad_size: CRVAL(2), CRPIX(2), CD(4), AP, BP (square layouts);
+// one thread per entry.
+__global__ __launch_bounds__(128) void bwd_chain(const double *__restrict__ totals, WcsJacobian J,
+                                                 int s_order, int ap_order, int bp_order, double S,
+                                                 double *__restrict__ grad) {
   const int NC = (s_order + 1) * (s_order + 2) / 2;
-  for (int k = 0; k < 2; ++k) {
+  const int na = ap_order > 0 ? (ap_order + 1) * (ap_order + 1) : 0;
+  const int nb = bp_order > 0 ? (bp_order + 1) * (bp_order + 1) : 0;
+  const int t = threadIdx.x;
+  if (t >= 8 + na + nb) return;
+  if (t < 2 || (t >= 4 && t < 8)) {
+    // CRVAL_k (t < 2) or CD_kl (t = 4 + kl) through dH/dtheta
+    const int row = t < 2 ? t : 2 + (t - 4);
     double g = 0.0;
-    for (int i = 0; i < 9; ++i) g += totals[i] * J.dh[k * 9 + i];
-    grad[k] = g;
+    for (int i = 0; i < 9; ++i) g += totals[i] * J.dh[row * 9 + i];
+    grad[t] = g;
+    return;
   }
-  grad[2] = totals[9];
-  grad[3] = totals[10];
-  for (int kl = 0; kl < 4; ++kl) {
-    double g = 0.0;
-    for (int i = 0; i < 9; ++i) g += totals[i] * J.dh[(2 + kl) * 9 + i];
-    grad[4 + kl] = g;
+  if (t < 4) {
+    grad[t] = totals[9 + (t - 2)];  // CRPIX
+    return;
   }
-  int off = 8;
-  const int orders[2] = {ap_order, bp_order};
-  for (int poly = 0; poly < 2; ++poly) {
-    const int o = orders[poly];
-    if (o <= 0) continue;
-    for (int p = 0; p <= o; ++p)
-      for (int q = 0; q <= o; ++q) {
-        double v = 0.0;
-        if (p + q <= o) {
-          double sc = 1.0;
-          for (int i = 0; i < p + q; ++i) sc *= S;
-          v = totals[11 + poly * NC + tri_n(s_order, p, q)] * sc;
-        }
-        grad[off + p * (o + 1) + q] = v;
-      }
-    off += (o + 1) * (o + 1);
+  const int poly = t - 8 < na ? 0 : 1;
+  const int o = poly == 0 ? ap_order : bp_order;
+  const int idx = t - 8 - (poly == 0 ? 0 : na);
+  const int p = idx / (o + 1), q = idx % (o + 1);
+  double v = 0.0;
+  if (p + q <= o) {
+    double sc = 1.0;
+    for (int i = 0; i < p + q; ++i) sc *= S;
+    v = totals[11 + poly * NC + tri_n(s_order, p, q)] * sc;
   }
+  grad[t] = v;
 }
 
 hipError_t launch_backward_finish(const double *partials, int n_blocks, int n_sums,
@@ -728,7 +635,7 @@ hipError_t launch_backward_finish(const double *partials, int n_blocks, int n_su
                      totals);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !grad_wcs) return e;
-  hipLaunchKernelGGL(bwd_chain, dim3(1), dim3(64), 0, stream, totals, jac, s_order, ap_order,
+  hipLaunchKernelGGL(bwd_chain, dim3(1), dim3(128), 0, stream, totals, jac, s_order, ap_order,
                      bp_order, s_scale, grad_wcs);
   return hipGetLastError();
 }
@@ -742,7 +649,26 @@ __global__ __launch_bounds__(256) void sq_residual_kernel(const float *__restric
                                                           float *__restrict__ gout) {
   __shared__ double ws[4];
   double acc = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+  // four elements per step with 16-byte loads and stores when every buffer
+  // is 16-byte aligned; element by element otherwise and for the tail
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const bool vec = ((reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(ref) |
+                     reinterpret_cast<uintptr_t>(mask) | reinterpret_cast<uintptr_t>(gout)) &
+                    15) == 0;
+  const int64_t n4 = vec ? n / 4 : 0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) {
+    const f4v o = reinterpret_cast<const f4v *>(out)[i];
+    const f4v r0 = reinterpret_cast<const f4v *>(ref)[i];
+    const f4v m = mask ? reinterpret_cast<const f4v *>(mask)[i] : (f4v){1.0f, 1.0f, 1.0f, 1.0f};
+    const f4v r = o - r0;
+    acc += (double)m.x * (double)r.x * (double)r.x;
+    acc += (double)m.y * (double)r.y * (double)r.y;
+    acc += (double)m.z * (double)r.z * (double)r.z;
+    acc += (double)m.w * (double)r.w * (double)r.w;
+    if (gout) reinterpret_cast<f4v *>(gout)[i] = 2.0f * m * r;
+  }
+  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     float r = out[i] - ref[i];
     float m = mask ? mask[i] : 1.0f;
     acc += (double)m * (double)r * (double)r;

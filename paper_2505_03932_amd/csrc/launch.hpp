@@ -82,13 +82,12 @@ struct WcsJacobian {
   double dh[54];  // dH_i / d theta_k at [k * 9 + i], theta = CRVAL1..2, CD1_1..CD2_2
 };
 
-// det_acc non-null: the deterministic source adjoint (grad_src unused here):
-// integer sums into det_acc [src_h][src_w], quantised with the scale from
-// gmax_bits (launch_det_prepare); launch_det_finish writes grad_src.
+// src_acc non-null: the source adjoint too, as integer sums into src_acc
+// [src_h][src_w] (zeroed by the caller), quantised with the scale from
+// gmax_bits (launch_det_prepare); launch_det_finish then writes grad_src.
 hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, int np,
-                           const float *grad_out, float *grad_src, int64_t gsrc_pitch,
-                           double *partials, unsigned long long *det_acc, const int *gmax_bits,
-                           hipStream_t stream);
+                           const float *grad_out, double *partials, unsigned long long *src_acc,
+                           const int *gmax_bits, hipStream_t stream);
 // max |g| into *gmax_bits (which must start at 0).
 hipError_t launch_det_prepare(const float *grad_out, int64_t n, int *gmax_bits,
                               hipStream_t stream);
