@@ -223,18 +223,18 @@ dfr_status dfr_reproject(const float *src, int32_t src_h, int32_t src_w, int64_t
   if (!out) return DFR_E_NULL;
   if (src_h == 0 || src_w == 0) src = nullptr;
   FramePlan P;
-  build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, out, footprint, P);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipError_t e;
   if (is_f32(o)) {
     TileGeom G;
     TileShape ts;
-    int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false);
-    make_geom(P, out_h, out_w, (int)interp, tile, o, G, ts);
+    single_setup(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, out, footprint,
+                 (int)interp, o, P, G, ts);
     std::lock_guard<std::mutex> lk(workspace_mutex());
     if ((s = models_for(P, out_h, out_w, o, st)) != DFR_OK) return s;
     e = launch_forward_f32(P, G, (int)interp, ts.np, st);
   } else {
+    build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, out, footprint, P);
     TrigPlan T;
     build_trig_plan(*src_wcs, *tgt_wcs, T);
     TileGeom G;
@@ -259,14 +259,13 @@ dfr_status dfr_reproject_noalloc(const float *src, int32_t src_h, int32_t src_w,
   if (!out) return DFR_E_NULL;
   if (src_h == 0 || src_w == 0) src = nullptr;
   FramePlan P;
-  build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, out, footprint, P);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   hipError_t e;
   if (is_f32(o)) {
     TileGeom G;
     TileShape ts;
-    int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false);
-    make_geom(P, out_h, out_w, (int)interp, tile, o, G, ts);
+    single_setup(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, out, footprint,
+                 (int)interp, o, P, G, ts);
     P.models = nullptr;
     if (o.precision == DFR_PREC_F32 && P.t_order == 0) {
       // the model table goes to the device's fixed scratch, not the
@@ -283,6 +282,7 @@ dfr_status dfr_reproject_noalloc(const float *src, int32_t src_h, int32_t src_w,
     }
     e = launch_forward_f32(P, G, (int)interp, ts.np, st);
   } else {
+    build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, out, footprint, P);
     TrigPlan T;
     build_trig_plan(*src_wcs, *tgt_wcs, T);
     TileGeom G;
@@ -534,23 +534,14 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
   // converted into grad_src (every entry written)
   const bool det = grad_src && src_h > 0 && src_w > 0;
   FramePlan P;
-  build_plan(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, nullptr, nullptr, P);
   o.debug_positions = nullptr;
   TileGeom G;
   TileShape ts;
-  std::memset(&G, 0, sizeof(G));
-  if (out_h > 0 && out_w > 0) {
-    // LDS: the source box and, for the source adjoint, its 64-bit integer
-    // accumulation copy
-    const int lds_factor = det ? 3 : 1;
-    int tile = choose_tile(P, out_h, out_w, (int)interp, o.tile, false, lds_factor,
-                           backward_default_tile((int)interp, grad_src != nullptr));
-    TileShape t4;
-    // the backward kernel runs 1 or 2 rows per thread: 4-row tiles use
-    // their 2-row sibling of the same width
-    if (tile_shape(tile, t4) && t4.np == 4) tile -= 1;
-    make_geom(P, out_h, out_w, (int)interp, tile, o, G, ts, lds_factor);
-  }
+  // LDS: the source box and, for the source adjoint, its 64-bit integer
+  // accumulation copy; 4-row tiles run as their 2-row sibling
+  single_setup(src, src_h, src_w, src_pitch, *src_wcs, *tgt_wcs, out_h, out_w, nullptr, nullptr,
+               (int)interp, o, P, G, ts, det ? 3 : 1,
+               backward_default_tile((int)interp, grad_src != nullptr), true);
   const int ns = backward_sums(P.s_order);
   WcsJacobian J;
   h_jacobian(*src_wcs, *tgt_wcs, J.dh);

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <unordered_map>
 
 #include "plan.hpp"
 
@@ -20,6 +21,7 @@ namespace {
 std::mutex g_tune_mutex;
 std::map<std::string, int> g_tune;
 bool g_tune_loaded = false;
+uint64_t g_tune_generation = 0;  // bumped whenever g_tune changes
 
 const char *cache_path() {
   const char *p = std::getenv("DFR_TUNE_CACHE");
@@ -108,6 +110,7 @@ void tune_store(const std::string &key, int tile) {
   std::lock_guard<std::mutex> lk(g_tune_mutex);
   load_cache_locked();
   g_tune[key] = tile;
+  ++g_tune_generation;
   save_cache_locked();
 }
 
@@ -157,6 +160,94 @@ void make_geom(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, int
   G.n_tiles = (int32_t)(G.tiles_x * ty);
   int64_t need = (int64_t)lds_factor * estimate_lds_floats(P, out_h, out_w, ts, interp);
   G.lds_cap = need <= kLdsMaxFloats ? (int32_t)need : 0;
+  G.cubic_a = (float)o.cubic_a;
+  G.nan_outside = o.nan_outside ? 1 : 0;
+  G.debug = o.debug_positions;
+  G.allow_skip = o.debug_positions ? 0 : 1;
+}
+
+// ------------------------------------------------ cached single set-up --
+
+namespace {
+
+struct SetupEntry {
+  FramePlan P;
+  TileGeom G;
+  TileShape ts;
+};
+
+std::mutex g_setup_mutex;
+std::unordered_map<std::string, SetupEntry> g_setup;
+constexpr size_t kSetupCacheMax = 256;
+
+void put_bytes(std::string &k, const void *p, size_t n) {
+  k.append(static_cast<const char *>(p), n);
+}
+
+void put_wcs(std::string &k, const dfr_wcs &w) {
+  put_bytes(k, w.crpix, sizeof(w.crpix));
+  put_bytes(k, w.crval, sizeof(w.crval));
+  put_bytes(k, w.cd, sizeof(w.cd));
+  const int32_t orders[4] = {w.a_order, w.b_order, w.ap_order, w.bp_order};
+  put_bytes(k, orders, sizeof(orders));
+  const double *coef[4] = {w.a, w.b, w.ap, w.bp};
+  for (int i = 0; i < 4; ++i)
+    if (orders[i] > 0 && coef[i])
+      put_bytes(k, coef[i], sizeof(double) * (orders[i] + 1) * (orders[i] + 1));
+}
+
+}  // namespace
+
+void single_setup(const float *src, int32_t src_h, int32_t src_w, int64_t src_pitch,
+                  const dfr_wcs &sw, const dfr_wcs &tw, int32_t out_h, int32_t out_w,
+                  float *out, float *footprint, int interp, const dfr_options &o, FramePlan &P,
+                  TileGeom &G, TileShape &ts, int lds_factor, int pref, bool two_rows) {
+  std::string key;
+  key.reserve(1024);
+  uint64_t gen;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    load_cache_locked();
+    gen = g_tune_generation;
+  }
+  const int64_t ints[9] = {src_h, src_w, out_h, out_w, interp, o.tile, lds_factor, pref,
+                           two_rows ? 1 : 0};
+  put_bytes(key, ints, sizeof(ints));
+  put_bytes(key, &gen, sizeof(gen));
+  put_wcs(key, sw);
+  put_wcs(key, tw);
+  bool hit = false;
+  {
+    std::lock_guard<std::mutex> lk(g_setup_mutex);
+    auto it = g_setup.find(key);
+    if (it != g_setup.end()) {
+      P = it->second.P;
+      G = it->second.G;
+      ts = it->second.ts;
+      hit = true;
+    }
+  }
+  if (!hit) {
+    build_plan(nullptr, src_h, src_w, src_w, sw, tw, out_h, out_w, nullptr, nullptr, P);
+    std::memset(&G, 0, sizeof(G));
+    std::memset(&ts, 0, sizeof(ts));
+    if (out_h > 0 && out_w > 0) {
+      int tile = choose_tile(P, out_h, out_w, interp, o.tile, false, lds_factor, pref);
+      TileShape t4;
+      if (two_rows && tile_shape(tile, t4) && t4.np == 4) tile -= 1;
+      dfr_options base;
+      dfr_options_init(&base);
+      make_geom(P, out_h, out_w, interp, tile, base, G, ts, lds_factor);
+    }
+    std::lock_guard<std::mutex> lk(g_setup_mutex);
+    if (g_setup.size() >= kSetupCacheMax) g_setup.clear();
+    g_setup[key] = SetupEntry{P, G, ts};
+  }
+  // the per-call parts
+  P.src = (src_h > 0 && src_w > 0) ? src : nullptr;
+  P.pitch = src_pitch;
+  P.out = out;
+  P.fp = footprint;
   G.cubic_a = (float)o.cubic_a;
   G.nan_outside = o.nan_outside ? 1 : 0;
   G.debug = o.debug_positions;

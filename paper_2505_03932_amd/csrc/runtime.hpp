@@ -29,6 +29,21 @@ void tune_store(const std::string &key, int tile);
 int tuned_tile(const std::string &key);
 std::mutex &tune_mutex_for_batch();
 
+// Host set-up of a single-image FP32 call (the FP64 plan, the tile choice
+// and the launch geometry), cached per geometry: the key holds the bytes of
+// both WCS and their SIP coefficients, the shapes, the interpolation, the
+// requested tile and the tuned-tile cache's generation, so a hit is exactly
+// what the set-up would compute again.  Image pointers and the per-call
+// options (cubic a, NaN outside, debug output) are filled in on every call.
+// The backward's set-up passes lds_factor (copies of the box it keeps), its
+// untuned tile preference, and two_rows (4-row tiles run as their 2-row
+// sibling of the same width).
+void single_setup(const float *src, int32_t src_h, int32_t src_w, int64_t src_pitch,
+                  const dfr_wcs &sw, const dfr_wcs &tw, int32_t out_h, int32_t out_w,
+                  float *out, float *footprint, int interp, const dfr_options &o, FramePlan &P,
+                  TileGeom &G, TileShape &ts, int lds_factor = 1, int pref = 0,
+                  bool two_rows = false);
+
 // lds_factor: copies of the source box a kernel keeps (backward: 2).
 void make_geom(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, int tile,
                const dfr_options &o, TileGeom &G, TileShape &ts, int lds_factor = 1);
