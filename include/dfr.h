@@ -51,7 +51,7 @@ extern "C" {
 #endif
 
 #define DFR_MAX_SIP_ORDER 9
-#define DFR_ABI_VERSION 2
+#define DFR_ABI_VERSION 3
 
 typedef struct dfr_wcs {
   double crpix[2];       /* CRPIX1, CRPIX2 (1-based)                              */
@@ -320,12 +320,16 @@ dfr_status dfr_check_wcs(const dfr_wcs *wcs, int32_t as_source);
  * denominator that may vanish in the cell), `certified` 1 when the kernels
  * use the model: the part of the bound the cubic leaves out of the map is
  * <= 1e-6 px (the rest is the FP32 rounding of the coefficients, about
- * 6e-8 of their contributions, which the FP32 chain shares).  All outputs are host pointers and may
- * be NULL.  Errors: DFR_E_NULL (a WCS is NULL), DFR_E_WCS /
+ * 6e-8 of their contributions, which the FP32 chain shares).  `tie` receives
+ * the distance from a rounding tie within which nearest decides a pixel of
+ * the cell from an FP64 position: twice the bound on |FP32 evaluation of the
+ * model - exact position| (`bound` plus the FP32 rounding of Horner's rule,
+ * gamma_6 sum_k |coef_k| 15.5^(i+j)), at least 1e-6 (0.5 where no model
+ * exists).  All outputs are host pointers and may be NULL.  Errors: DFR_E_NULL (a WCS is NULL), DFR_E_WCS /
  * DFR_E_UNSUPPORTED as dfr_reproject, DFR_E_ARG (cx or cy negative). */
 dfr_status dfr_cell_model(const dfr_wcs *src_wcs, const dfr_wcs *tgt_wcs, int32_t cx, int32_t cy,
                           double coef_x[10], double coef_y[10], int32_t base[2], double *bound,
-                          int32_t *certified);
+                          int32_t *certified, double *tie);
 
 /* Free cached per-device workspaces and graphs (the calling thread's device). */
 dfr_status dfr_release(void);

@@ -121,7 +121,7 @@ def _load():
     L.dfr_check_wcs.argtypes = [W, i32]
     L.dfr_check_wcs.restype = st
     D = C.POINTER(C.c_double)
-    L.dfr_cell_model.argtypes = [W, W, i32, i32, D, D, C.POINTER(i32), D, C.POINTER(i32)]
+    L.dfr_cell_model.argtypes = [W, W, i32, i32, D, D, C.POINTER(i32), D, C.POINTER(i32), D]
     L.dfr_cell_model.restype = st
     L.dfr_release.argtypes = []
     L.dfr_release.restype = st
@@ -251,13 +251,13 @@ def dfr_check_wcs(wcs, as_source: bool) -> int:
 
 
 def dfr_cell_model(src_wcs, tgt_wcs, cx: int, cy: int):
-    """Returns (status, coef_x[10], coef_y[10], (base_x, base_y), bound, certified)."""
+    """Returns (status, coef_x[10], coef_y[10], (base_x, base_y), bound, certified, tie)."""
     cxs, cys = (C.c_double * 10)(), (C.c_double * 10)()
     base = (C.c_int32 * 2)()
-    bound, cert = C.c_double(0.0), C.c_int32(0)
+    bound, cert, tie = C.c_double(0.0), C.c_int32(0), C.c_double(0.0)
     s = lib.dfr_cell_model(C.byref(src_wcs), C.byref(tgt_wcs), cx, cy, cxs, cys, base,
-                           C.byref(bound), C.byref(cert))
-    return s, list(cxs), list(cys), (base[0], base[1]), bound.value, cert.value
+                           C.byref(bound), C.byref(cert), C.byref(tie))
+    return s, list(cxs), list(cys), (base[0], base[1]), bound.value, cert.value, tie.value
 
 
 def dfr_release() -> int:

@@ -516,12 +516,13 @@ def sq_residual(out, ref, mask=None, want_grad=True):
 
 def cell_model(src_wcs, tgt_wcs, cx: int, cy: int) -> dict:
     """The local position model of output cell (cx, cy) the default FP32 path
-    evaluates (host only): FP32 coefficients, integer base, certified bound."""
-    s, mx, my, base, bound, cert = _lib.dfr_cell_model(CWcs(src_wcs).s, CWcs(tgt_wcs).s,
-                                                      int(cx), int(cy))
+    evaluates (host only): FP32 coefficients, integer base, certified bound,
+    and the distance from a rounding tie within which nearest decides in FP64."""
+    s, mx, my, base, bound, cert, tie = _lib.dfr_cell_model(CWcs(src_wcs).s, CWcs(tgt_wcs).s,
+                                                           int(cx), int(cy))
     _check(s, "dfr_cell_model")
     return {"coef_x": np.array(mx), "coef_y": np.array(my), "base": base, "bound": bound,
-            "certified": bool(cert)}
+            "certified": bool(cert), "tie": tie}
 
 
 def release():

@@ -695,7 +695,7 @@ void dfr_cd_from_pc_cdelt(const double pc[4], const double cdelt[2], double cd[4
 
 dfr_status dfr_cell_model(const dfr_wcs *src_wcs, const dfr_wcs *tgt_wcs, int32_t cx, int32_t cy,
                           double coef_x[10], double coef_y[10], int32_t base[2], double *bound,
-                          int32_t *certified) {
+                          int32_t *certified, double *tie) {
   if (!src_wcs || !tgt_wcs) return DFR_E_NULL;
   if (cx < 0 || cy < 0 || cx >= (1 << 25) || cy >= (1 << 25)) return DFR_E_ARG;
   dfr_status s;
@@ -716,6 +716,7 @@ dfr_status dfr_cell_model(const dfr_wcs *src_wcs, const dfr_wcs *tgt_wcs, int32_
   }
   if (bound) *bound = M.err;
   if (certified) *certified = M.certified;
+  if (tie) *tie = M.tie;
   return DFR_OK;
 }
 

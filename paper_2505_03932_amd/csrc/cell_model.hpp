@@ -36,7 +36,8 @@ struct alignas(16) CellModel {
   int32_t bx, by;        // integer part of the source position at the cell centre
   float err;             // certified bound on |model - map| over the cell (px)
   int32_t certified;     // 1: truncation <= kModelTol and every pixel has a valid position
-  int32_t pad_[2];
+  float tie;             // nearest: FP32 positions this close to a rounding tie are decided in FP64
+  int32_t pad_;
 };
 static_assert(sizeof(CellModel) == 112, "CellModel layout");
 
@@ -152,7 +153,8 @@ __host__ __device__ inline void cell_model(const FramePlan &P, int cx, int cy, C
   M.bx = M.by = 0;
   M.err = 1.0e30f;
   M.certified = 0;
-  M.pad_[0] = M.pad_[1] = 0;
+  M.tie = 0.5f;
+  M.pad_ = 0;
   if (P.t_order > 0) return;  // the target SIP is not modelled
 
   const double uc = (double)cx * kCell + h - P.tcr[0], vc = (double)cy * kCell + h - P.tcr[1];
@@ -275,6 +277,24 @@ __host__ __device__ inline void cell_model(const FramePlan &P, int cx, int cy, C
   const double err = __builtin_fmax(errx, erry);
   if (!(err < 1.0e6)) return;
   M.err = (float)(err * (1.0 + 1.0e-6));
+  // The FP32 evaluation of the stored cubic (Horner's rule with fused
+  // multiply-adds in b, then in a) is within gamma_6 * S of the cubic's exact
+  // value, S = sum_k |m_k| h^(i+j) (the Horner bound gamma_n sum |c_j| |x|^j
+  // for each level, composed), so an FP32 position is within
+  // E = err + gamma_6 * S of the map; nearest decides the pixels within 2E of
+  // a rounding tie in FP64.
+  {
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+      const double hd = hp[cm_i(k) + cm_j(k)];
+      sx += __builtin_fabs((double)M.mx[k]) * hd;
+      sy += __builtin_fabs((double)M.my[k]) * hd;
+    }
+    const double u = 0x1p-24, g6 = 6.0 * u / (1.0 - 6.0 * u);
+    const double t = 2.0 * (err + g6 * __builtin_fmax(sx, sy)) * (1.0 + 1.0e-6);
+    M.tie = (float)__builtin_fmin(0.5, __builtin_fmax(t, 1.0e-6));  // >= 1e-6: 0.5f - tie rounds by < 3e-8
+  }
   M.ex = (float)((nlx + errx + kModelSlack) * (1.0 + 1.0e-6));
   M.ey = (float)((nly + erry + kModelSlack) * (1.0 + 1.0e-6));
   // the coefficient rounding is the FP32 evaluation error every FP32 path has

@@ -114,7 +114,7 @@ __device__ __forceinline__ bool vector_stores_ok(const FramePlan &P, const TileG
 }
 
 // Nearest: the FP64 rounding decision for a pixel whose FP32 position lies
-// within 1e-4 px of a tie (rare).  Writes the rounded position relative to
+// within reach of its FP32 error of a tie (rare).  Writes the rounded position relative to
 // (bx, by); returns false if the pixel has no source position.
 template <int SORD, bool TSIP>
 __device__ __forceinline__ bool nearest_exact(const FramePlan &P, int x, int y, int bx,
@@ -275,6 +275,17 @@ __device__ __forceinline__ void model_row(const CellModel &M, float b, ModelRow 
 __device__ __forceinline__ void model_at(const ModelRow &R, float a, float &px, float &py) {
   px = fmaf(fmaf(fmaf(R.x3, a, R.x2), a, R.x1), a, R.x0);
   py = fmaf(fmaf(fmaf(R.y3, a, R.y2), a, R.y1), a, R.y0);
+}
+
+// The model's position (relative to its base) at offsets (a, b) from the
+// cell centre, evaluated in FP64 from the stored coefficients: within
+// M.err of the map (the bound covers the coefficients' FP32 rounding), with
+// an evaluation error far below that.
+__device__ __forceinline__ double model_f64(const float m[10], double a, double b) {
+  const double c0 = fma(fma(fma((double)m[3], b, (double)m[2]), b, (double)m[1]), b, (double)m[0]);
+  const double c1 = fma(fma((double)m[6], b, (double)m[5]), b, (double)m[4]);
+  const double c2 = fma((double)m[8], b, (double)m[7]);
+  return fma(fma(fma((double)m[9], a, c2), a, c1), a, c0);
 }
 
 // Debug output: the FP64 source position of output pixel (x, y) as the

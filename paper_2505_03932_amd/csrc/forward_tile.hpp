@@ -373,9 +373,20 @@ struct FwdPos {
   unsigned tie;          // nearest, deferred: pixel (k, e) needs the FP64 decision
 };
 
+// Nearest: whether the FP32 position (px, py) lies closer to a rounding tie
+// than 0.5 - lim on either axis (x - rint(x) is exact in FP32).
+__device__ __forceinline__ bool near_tie(float px, float py, float lim) {
+  return fmaxf(fabsf(px - rintf(px)), fabsf(py - rintf(py))) > lim;
+}
+
+// FP32 positions of the anchored chain: within 1e-4 px of a tie they are
+// decided in FP64 (at least 5x that chain's FP32 error).
+constexpr float kAnchorTieLim = 0.4999f;
+
 // Phase 3: every pixel's position from its cell's model or anchor (sh.cell).
-// Nearest: a pixel whose FP32 position lies within 1e-4 px of a rounding
-// tie is decided from its FP64 position, here (DEFER false) or after the
+// Nearest: a pixel whose FP32 position lies within reach of its FP32 error
+// of a rounding tie (the model's rigorous M.tie, or 1e-4 px for an anchored
+// cell) is decided from an FP64 position, here (DEFER false) or after the
 // gather by nearest_ties (DEFER true: only a bit is kept here, so the FP64
 // chain's registers are not live across the tile's main work).
 template <int INTERP, int SORD, int NP, bool DEFER>
@@ -397,6 +408,7 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
       const CellModel &M = sh.cell[((y >> kCellLog2) - T.cy0) * T.ncx + ((xr >> kCellLog2) - T.cx0)].model;
       R.abx[k] = M.bx - B.bi0;
       R.aby[k] = M.by - B.bj0;
+      const float lim = 0.5f - M.tie;
       ModelRow Rw;
       model_row(M, (float)(y & (kCell - 1)) - hc, Rw);
       const float a0 = (float)(xr & (kCell - 1)) - hc;
@@ -406,8 +418,7 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
         model_at(Rw, a0 + (float)e, px, py);
         if constexpr (INTERP == DFR_NEAREST) {
           // a rounding decision within reach of the FP32 error: decide in FP64
-          float tx_ = px - floorf(px), ty_ = py - floorf(py);
-          if (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f) {
+          if (near_tie(px, py, lim)) {
             if constexpr (DEFER) {
               R.tie |= 1u << (k * kRun + e);
             } else {
@@ -432,6 +443,7 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
       const int bx = mk ? M.bx : A.bx, by = mk ? M.by : A.by;
       R.abx[k] = bx - B.bi0;
       R.aby[k] = by - B.bj0;
+      const float lim = mk ? 0.5f - M.tie : kAnchorTieLim;
       ModelRow Rw;
       if (mk) model_row(M, (float)(y & (kCell - 1)) - hc, Rw);
       const float dy = (float)(y & (kCell - 1));
@@ -453,8 +465,7 @@ __device__ __forceinline__ void tile_positions(const FramePlan &P, const TileGeo
         bool exact = false;
         if constexpr (INTERP == DFR_NEAREST) {
           // a rounding decision within reach of the FP32 error: decide in FP64
-          float tx_ = px - floorf(px), ty_ = py - floorf(py);
-          if (ok && (fabsf(tx_ - 0.5f) < 1e-4f || fabsf(ty_ - 0.5f) < 1e-4f)) {
+          if (ok && near_tie(px, py, lim)) {
             if constexpr (DEFER) {
               R.tie |= 1u << (k * kRun + e);
             } else {
@@ -573,19 +584,26 @@ __device__ __forceinline__ void CropSink::uncovered(const FramePlan &P, const Ti
 }
 
 // Nearest, after the gather: the pixels flagged in `tie` (bit k * kRun + e
-// for pixel e of run k) take their FP64 position, are rounded from it and
-// stored again, with the position for the debug output.  The wave first
-// waits for its earlier stores, so the correction is the last write to
-// those addresses.  The source value is read from global memory (these
-// pixels are rare).  It runs at the end of the tile, where little else is
-// live, so the FP64 chain adds no registers to the tile's main work.
+// for pixel e of run k) are rounded from an FP64 position and stored again,
+// with that position for the debug output.  In a cell with a certified
+// model the model is evaluated in FP64 first: it lies within M.err of the
+// map, so where both coordinates are farther than M.err + 1e-9 px from a
+// rounding tie it decides exactly as the FP64 chain would (whose own error
+// is far below 1e-9 px); only the rest take the full FP64 chain.  A wave's vector
+// stores are performed in the order it issues them, so the correction is
+// the last write to its address without waiting for the earlier stores; the
+// source value comes from the staged box (still intact: the group has not
+// passed its next barrier), so no vector-memory load has to wait behind
+// those stores either (on this architecture one counter covers loads and
+// stores).  It runs at the end of the tile, where little else is live, so
+// the FP64 chain adds no registers to the tile's main work.
 template <int SORD, int NP, class Sink>
 __device__ __forceinline__ void nearest_ties(const FramePlan &P, const TileGeom &G,
-                                             const TileXY &T, const FwdShared &sh, unsigned tie,
-                                             Sink &sink) {
+                                             const TileXY &T, const FwdShared &sh,
+                                             const TileBox &B, const float *__restrict__ lds,
+                                             unsigned tie, Sink &sink) {
   constexpr bool TSIP = SORD == kRtOrder;
   const float miss = G.nan_outside ? __builtin_nanf("") : 0.0f;
-  __builtin_amdgcn_s_waitcnt(0);
   while (tie) {
     const int bit = __builtin_ctz(tie);
     tie &= tie - 1u;
@@ -597,12 +615,30 @@ __device__ __forceinline__ void nearest_ties(const FramePlan &P, const TileGeom 
     const int by = mk ? sh.cell[ci].model.by : sh.cell[ci].anchor.by;
     float px = 0.0f, py = 0.0f;
     double xs = 0.0, ys = 0.0;
-    const bool ok = nearest_exact<SORD, TSIP>(P, x, y, bx, by, px, py, xs, ys);
+    bool decided = false;
+    if (mk) {
+      const CellModel &M = sh.cell[ci].model;
+      const double a = (double)(x & (kCell - 1)) - kHalfCell;
+      const double b = (double)(y & (kCell - 1)) - kHalfCell;
+      const double mxv = model_f64(M.mx, a, b), myv = model_f64(M.my, a, b);
+      const double tol = (double)M.err + 1.0e-9;
+      if (fabs(mxv - floor(mxv) - 0.5) > tol && fabs(myv - floor(myv) - 0.5) > tol) {
+        px = (float)rint(mxv);
+        py = (float)rint(myv);
+        xs = (double)bx + mxv;
+        ys = (double)by + myv;
+        decided = true;
+      }
+    }
+    const bool ok = decided || nearest_exact<SORD, TSIP>(P, x, y, bx, by, px, py, xs, ys);
     float o = miss, f = 0.0f;
     if (ok) {
       const int i = bx + (int)px, j = by + (int)py;
       if ((unsigned)i < (unsigned)P.src_w && (unsigned)j < (unsigned)P.src_h) {
-        o = global_ptr(P.src)[(int64_t)j * P.pitch + i];
+        if (B.use_lds && i >= B.bi0 && i <= B.bi1 && j >= B.bj0 && j <= B.bj1)
+          o = lds[__umul24(j - B.bj0, B.lp) + (i - B.bi0)];
+        else
+          o = global_ptr(P.src)[(int64_t)j * P.pitch + i];
         f = 1.0f;
       }
     }
@@ -631,7 +667,7 @@ __device__ __forceinline__ void forward_tile(const FramePlan &P, const TileGeom 
   __syncthreads();
   tile_gather<INTERP, NP>(P, G, T, B, lds, R, sink);
   if constexpr (kDefer) {
-    if (R.tie) nearest_ties<SORD, NP>(P, G, T, sh, R.tie, sink);
+    if (R.tie) nearest_ties<SORD, NP>(P, G, T, sh, B, lds, R.tie, sink);
   }
 }
 

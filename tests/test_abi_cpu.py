@@ -31,7 +31,7 @@ def test_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(L.lib, n), n
     assert set(names) == set(L.EXPORTED)
-    assert L.dfr_abi_version() == 2
+    assert L.dfr_abi_version() == 3
 
 
 def test_struct_sizes_match_header(L):

@@ -104,6 +104,98 @@ def test_batch_frames_certified(dfr, orc):
             assert m["certified"]
 
 
+def fma32(a, b, c):
+    """Correctly rounded FP32 fused multiply-add of FP32 arrays: the product is
+    exact in FP64, TwoSum gives the FP64 sum's error, and a sum that lands
+    exactly halfway between two FP32 values is rounded by that error's sign."""
+    p = a.astype(np.float64) * b.astype(np.float64)
+    c64 = c.astype(np.float64)
+    s = p + c64
+    bb = s - p
+    e = (p - (s - bb)) + (c64 - bb)
+    r = s.astype(np.float32)
+    r64 = r.astype(np.float64)
+    toward = np.where(s > r64, np.float32(np.inf), np.float32(-np.inf)).astype(np.float32)
+    n = np.nextafter(r, toward)
+    half = (s != r64) & (s == (r64 + n.astype(np.float64)) / 2)
+    up = half & (((e > 0) & (n > r)) | ((e < 0) & (n < r)))
+    down = half & (((e > 0) & (n < r)) | ((e < 0) & (n > r)))
+    out = r.copy()
+    out[up | down] = n[up | down]
+    # a halfway sum with e == 0 keeps FP32's round-to-even, which astype did
+    return out
+
+
+def model_fp32(m):
+    """The cell's positions relative to its base as the kernels compute them:
+    per row a cubic in b (coefficients by Horner with fused multiply-adds),
+    then Horner in a, all in FP32."""
+    ys, xs = np.mgrid[0:CELL, 0:CELL]
+    a = (xs.astype(np.float32) - np.float32(HALF)).ravel()
+    b = (ys.astype(np.float32) - np.float32(HALF)).ravel()
+    out = []
+    for cf in (m["coef_x"], m["coef_y"]):
+        c = [np.full(a.shape, np.float32(v)) for v in cf]
+        r0 = fma32(fma32(fma32(c[3], b, c[2]), b, c[1]), b, c[0])
+        r1 = fma32(fma32(c[6], b, c[5]), b, c[4])
+        r2 = fma32(c[8], b, c[7])
+        out.append(fma32(fma32(fma32(c[9], a, r2), a, r1), a, r0))
+    return np.stack(out, axis=1).reshape(CELL, CELL, 2)
+
+
+def test_fma32_emulation():
+    """The FP32 fused multiply-add emulation against exact rational arithmetic."""
+    from fractions import Fraction
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=4000).astype(np.float32)
+    b = (rng.normal(size=4000) * 16).astype(np.float32)
+    c = (rng.normal(size=4000) * 30).astype(np.float32)
+    # include sums that land halfway between FP32 neighbours
+    a[:8] = np.float32(1.0) + np.float32(2.0 ** -23)
+    b[:8] = np.float32(1.0) + np.float32(2.0 ** -23)
+    c[:8] = np.float32(0.0)
+    got = fma32(a, b, c)
+    for i in range(len(a)):
+        exact = Fraction(float(a[i])) * Fraction(float(b[i])) + Fraction(float(c[i]))
+        lo = np.float32(float(exact))
+        cands = [np.nextafter(lo, np.float32(-np.inf)), lo, np.nextafter(lo, np.float32(np.inf))]
+        best = min(cands, key=lambda v: (abs(Fraction(float(v)) - exact),
+                                         int(np.frombuffer(np.float32(v).tobytes(), np.uint32)[0]) & 1))
+        assert got[i] == best, (i, a[i], b[i], c[i], got[i], best)
+
+
+@pytest.mark.parametrize("name", ["plain", "sip3", "grad", "pole", "batch"])
+def test_fp32_evaluation_within_tie_distance(dfr, orc, name):
+    """The nearest kernels take the FP32 rounding decision of a model cell
+    unless its FP32 position lies within `tie` of a rounding tie; that is
+    exact only if the FP32 evaluation stays within tie / 2 of the map, which
+    is checked here on every pixel of sampled cells."""
+    if name == "batch":
+        c = configs.batch(images=False)
+        frames = [(c.src_wcs[k], k) for k in (0, 29, 63)]
+        tw = c.tgt_wcs
+    else:
+        c = {"plain": lambda: configs.plain(), "sip3": lambda: configs.sip3(),
+             "grad": lambda: configs.grad(size=2048), "pole": lambda: configs.pole(size=2048)}[name]()
+        frames = [(c.src_wcs, 3)]
+        tw = c.tgt_wcs
+    worst_ratio, largest = 0.0, 0.0
+    for sw, seed in frames:
+        for cx, cy in sample_cells(c.out_shape, 10, seed):
+            m = dfr.cell_model(sw, tw, cx, cy)
+            assert m["certified"]
+            pos, valid = cell_positions(orc, sw, tw, cx, cy)
+            assert valid.all()
+            fp = model_fp32(m).astype(np.float64) + np.array(m["base"], np.float64)
+            err = np.abs(fp - pos).max()
+            # the oracle's own FP64 error is ~1e-10 px
+            assert err <= m["tie"] / 2 + 1e-9, (name, cx, cy, err, m["tie"])
+            assert 1e-6 <= m["tie"] <= 1e-4
+            worst_ratio = max(worst_ratio, err / (m["tie"] / 2))
+            largest = max(largest, m["tie"])
+    print(name, "largest tie distance", largest, "largest error / (tie / 2)", worst_ratio)
+
+
 def test_target_sip_has_no_model(dfr):
     c = configs.plain()
     a, b = draw_sip(2, 128.0, np.random.default_rng(1))
