@@ -533,7 +533,15 @@ __global__ __launch_bounds__(256) void abs_max_kernel(const float *__restrict__ 
                                                       int *__restrict__ bits) {
   __shared__ float wm[4];
   float m = 0.0f;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+  // 16-byte loads where the buffer is aligned, then the tail
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  const int64_t n4 = (reinterpret_cast<uintptr_t>(g) & 15) == 0 ? n / 4 : 0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) {
+    const f4v v = reinterpret_cast<const f4v *>(g)[i];
+    m = fmaxf(fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y))), fmaxf(fabsf(v.z), fabsf(v.w)));
+  }
+  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
     m = fmaxf(m, fabsf(g[i]));
   m = wave_max_f(m);
   if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
@@ -559,7 +567,7 @@ __global__ __launch_bounds__(256) void det_finish_kernel(const unsigned long lon
 
 hipError_t launch_det_prepare(const float *grad_out, int64_t n, int *gmax_bits,
                               hipStream_t stream) {
-  hipLaunchKernelGGL(abs_max_kernel, dim3((unsigned)std::min<int64_t>(512, std::max<int64_t>(1, (n + 255) / 256))),
+  hipLaunchKernelGGL(abs_max_kernel, dim3((unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (n + 1023) / 1024))),
                      dim3(256), 0, stream, grad_out, n, gmax_bits);
   return hipGetLastError();
 }
