@@ -545,37 +545,74 @@ dfr_status dfr_reproject_backward(const float *src, int32_t src_h, int32_t src_w
   const int ns = backward_sums(P.s_order);
   WcsJacobian J;
   h_jacobian(*src_wcs, *tgt_wcs, J.dh);
+  FinishArgs A;
+  A.ns = ns;
+  A.nr = grad_wcs ? ns - 10 : 0;
+  A.J = J;
+  A.S = P.s_scale;
+  A.grad_wcs = grad_wcs;
+  if (grad_wcs) {
+    // where each SIP column's total goes in the square AP/BP layouts, and
+    // which entries lie above their polynomial's order (zero)
+    const int NC = (P.s_order + 1) * (P.s_order + 2) / 2;
+    for (int k = 0; k < 2 * NC; ++k) A.col_entry[k] = -1;
+    A.n_above = 0;
+    int base = 8;
+    for (int poly = 0; poly < 2; ++poly) {
+      const int o = poly == 0 ? src_wcs->ap_order : src_wcs->bp_order;
+      if (o <= 0) continue;
+      for (int p = 0; p <= o; ++p)
+        for (int q = 0; q <= o; ++q) {
+          const int e = base + p * (o + 1) + q;
+          if (p + q <= o) {
+            const int k = poly * NC + tri_n(P.s_order, p, q);
+            A.col_entry[k] = e;
+            A.col_deg[k] = p + q;
+          } else {
+            A.above[A.n_above++] = e;
+          }
+        }
+      base += (o + 1) * (o + 1);
+    }
+  }
   std::lock_guard<std::mutex> lk(workspace_mutex());
   Workspace *w = workspace(st);
-  // workspace: per-tile FP64 partials and their totals; for the source
-  // adjoint also max|g| (as float bits) and the 64-bit integer sums
-  const size_t pbytes = ((size_t)std::max(G.n_tiles, 1) * ns + ns) * sizeof(double);
+  // workspace: per-tile FP64 partials; for the source adjoint also the
+  // 64-bit integer sums; max|g| (as float bits) alternates between two of
+  // the workspace's control words
+  const size_t pbytes = (size_t)std::max(G.n_tiles, 1) * ns * sizeof(double);
   const size_t qofs = (pbytes + 255) & ~(size_t)255;
-  const size_t bytes = det ? qofs + 256 + (size_t)src_h * src_w * sizeof(uint64_t) : pbytes;
+  const size_t bytes = det ? qofs + (size_t)src_h * src_w * sizeof(uint64_t) : pbytes;
   void *buf = nullptr;
+  int *ctl = nullptr;
   if ((s = workspace_buffer(w, bytes, &buf)) != DFR_OK) return s;
+  if ((s = workspace_control(w, &ctl)) != DFR_OK) return s;
   double *part = static_cast<double *>(buf);
-  double *totals = part + (size_t)std::max(G.n_tiles, 1) * ns;
-  int *gmax_bits = det ? reinterpret_cast<int *>(static_cast<char *>(buf) + qofs) : nullptr;
   unsigned long long *qacc =
-      det ? reinterpret_cast<unsigned long long *>(static_cast<char *>(buf) + qofs + 256) : nullptr;
-  if (det) {
-    // zero max|g| and the integer sums (kernels, not memsets), then max|g|
-    if (launch_zero_i32(gmax_bits, 1, st) != hipSuccess ||
-        launch_zero_f32(reinterpret_cast<float *>(qacc), src_h, 2 * (int64_t)src_w,
-                        2 * (int64_t)src_w, st) != hipSuccess ||
-        launch_det_prepare(grad_out, (int64_t)out_h * out_w, gmax_bits, st) != hipSuccess)
-      return DFR_E_DEVICE;
+      det ? reinterpret_cast<unsigned long long *>(static_cast<char *>(buf) + qofs) : nullptr;
+  int *gmax = ctl + w->ctl_slot, *gmax_next = ctl + (w->ctl_slot ^ 1);
+  A.partials = part;
+  A.n_blocks = G.n_tiles;
+  A.q = qacc;
+  A.h = det ? src_h : 0;
+  A.w = det ? src_w : 0;
+  A.gsrc = grad_src;
+  A.gpitch = src_w;
+  A.gmax = gmax;
+  // zero the integer sums and take max|g| (one kernel), the backward, then
+  // grad_src and the WCS gradient (one kernel); a launch that fails leaves
+  // the control words dirty
+  const bool ok =
+      (!det || launch_det_prepare(grad_out, (int64_t)out_h * out_w, qacc,
+                                  (int64_t)src_h * src_w, gmax, gmax_next, st) == hipSuccess) &&
+      (G.n_tiles <= 0 ||
+       launch_backward(P, G, (int)interp, ts.np, grad_out, part, qacc, gmax, st) == hipSuccess) &&
+      launch_backward_finish(A, st) == hipSuccess;
+  if (!ok) {
+    w->ctl_dirty = true;
+    return DFR_E_DEVICE;
   }
-  if (G.n_tiles > 0 &&
-      launch_backward(P, G, (int)interp, ts.np, grad_out, part, qacc, gmax_bits, st) !=
-          hipSuccess)
-    return DFR_E_DEVICE;
-  if (det && launch_det_finish(qacc, src_h, src_w, gmax_bits, grad_src, src_w, st) != hipSuccess)
-    return DFR_E_DEVICE;
-  if (launch_backward_finish(part, G.n_tiles, ns, totals, J, P.s_order, src_wcs->ap_order,
-                             src_wcs->bp_order, P.s_scale, grad_wcs, st) != hipSuccess)
-    return DFR_E_DEVICE;
+  if (det) w->ctl_slot ^= 1;
   return DFR_OK;
 }
 

@@ -526,125 +526,139 @@ hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, in
   return hipGetLastError();
 }
 
-// max |g| over the output gradient, as the bits of a non-negative float
-// (their integer order is the float order, so atomicMax gives the same
-// result in any order); *bits starts at 0.
-__global__ __launch_bounds__(256) void abs_max_kernel(const float *__restrict__ g, int64_t n,
-                                                      int *__restrict__ bits) {
+// Before the backward kernel, for the source adjoint, in one launch: the
+// 64-bit integer image is zeroed and max |g| over the output gradient is
+// folded into *gmax as the bits of a non-negative float (their integer
+// order is the float order, so atomicMax gives the same result in any
+// order).  *gmax is 0 on entry; *gmax_next, the slot the next call uses, is
+// zeroed here (the previous call's kernels, which read it, have finished).
+__global__ __launch_bounds__(256) void det_prepare_kernel(const float *__restrict__ g, int64_t n,
+                                                          unsigned long long *__restrict__ q,
+                                                          int64_t nq, int *__restrict__ gmax,
+                                                          int *__restrict__ gmax_next) {
   __shared__ float wm[4];
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i0 == 0) *gmax_next = 0;
+  // the image is 16-byte aligned (a 256-byte aligned workspace offset)
+  typedef unsigned long long u2v __attribute__((ext_vector_type(2)));
+  for (int64_t i = i0; i < nq / 2; i += stride) reinterpret_cast<u2v *>(q)[i] = u2v{0ull, 0ull};
+  if (i0 == 0 && (nq & 1)) q[nq - 1] = 0ull;
   float m = 0.0f;
-  // 16-byte loads where the buffer is aligned, then the tail
+  // 16-byte loads where the gradient is aligned, then the tail
   typedef float f4v __attribute__((ext_vector_type(4)));
   const int64_t n4 = (reinterpret_cast<uintptr_t>(g) & 15) == 0 ? n / 4 : 0;
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) {
+  for (int64_t i = i0; i < n4; i += stride) {
     const f4v v = reinterpret_cast<const f4v *>(g)[i];
     m = fmaxf(fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y))), fmaxf(fabsf(v.z), fabsf(v.w)));
   }
-  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
-    m = fmaxf(m, fabsf(g[i]));
+  for (int64_t i = 4 * n4 + i0; i < n; i += stride) m = fmaxf(m, fabsf(g[i]));
   m = wave_max_f(m);
   if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
     m = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
-    if (m > 0.0f) atomicMax(bits, __float_as_int(m));  // one atomic per block
+    if (m > 0.0f) atomicMax(gmax, __float_as_int(m));  // one atomic per block
   }
 }
 
-// The source adjoint's integer sums back to float: grad_src = q 2^-Q.
-__global__ __launch_bounds__(256) void det_finish_kernel(const unsigned long long *__restrict__ q,
-                                                         int64_t h, int64_t w,
-                                                         const int *__restrict__ gmax_bits,
-                                                         float *__restrict__ gsrc,
-                                                         int64_t gpitch) {
-  const double inv = 1.0 / det_scale(gmax_bits);
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < h * w; i += (int64_t)gridDim.x * 256) {
-    const int64_t r = i / w, col = i - r * w;
-    gsrc[r * gpitch + col] = (float)((double)(long long)q[i] * inv);
-  }
-}
-
-hipError_t launch_det_prepare(const float *grad_out, int64_t n, int *gmax_bits,
-                              hipStream_t stream) {
-  hipLaunchKernelGGL(abs_max_kernel, dim3((unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (n + 1023) / 1024))),
-                     dim3(256), 0, stream, grad_out, n, gmax_bits);
+hipError_t launch_det_prepare(const float *grad_out, int64_t n, unsigned long long *q, int64_t nq,
+                              int *gmax, int *gmax_next, hipStream_t stream) {
+  const int64_t work = std::max<int64_t>(n / 4, nq / 2);
+  hipLaunchKernelGGL(det_prepare_kernel,
+                     dim3((unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (work + 255) / 256))),
+                     dim3(256), 0, stream, grad_out, n, q, nq, gmax, gmax_next);
   return hipGetLastError();
 }
 
-hipError_t launch_det_finish(const unsigned long long *q, int64_t h, int64_t w,
-                             const int *gmax_bits, float *grad_src, int64_t gpitch,
-                             hipStream_t stream) {
-  const int64_t n = h * w;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(det_finish_kernel, dim3((unsigned)std::min<int64_t>(4096, (n + 255) / 256)),
-                     dim3(256), 0, stream, q, h, w, gmax_bits, grad_src, gpitch);
-  return hipGetLastError();
-}
-
-// Column s of the [n_blocks][ns] partials, summed in a fixed order.
-__global__ __launch_bounds__(256) void bwd_reduce(const double *__restrict__ partials,
-                                                  int n_blocks, int ns,
-                                                  double *__restrict__ totals) {
-  __shared__ double sm[256];
-  const int s = blockIdx.x, tid = threadIdx.x;
+// Column c of the [n_blocks][ns] partials, summed by one block in a fixed
+// order (256 strided partial sums, then a tree); the result is in sm[0].
+__device__ __forceinline__ void column_sum(const FinishArgs &A, int c, double *sm) {
+  const int tid = threadIdx.x;
   double a = 0.0;
-  for (int b = tid; b < n_blocks; b += 256) a += partials[(int64_t)b * ns + s];
+#pragma unroll 4
+  for (int k = tid; k < A.n_blocks; k += 256) a += A.partials[(int64_t)k * A.ns + c];
   sm[tid] = a;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (tid < w) sm[tid] += sm[tid + w];
     __syncthreads();
   }
-  if (tid == 0) totals[s] = sm[0];
 }
 
-// Chain rule to the source WCS parameters, in the order of
-// dfr_wcs_grad_size: CRVAL(2), CRPIX(2), CD(4), AP, BP (square layouts);
-// one thread per entry.
-__global__ __launch_bounds__(128) void bwd_chain(const double *__restrict__ totals, WcsJacobian J,
-                                                 int s_order, int ap_order, int bp_order, double S,
-                                                 double *__restrict__ grad) {
-  const int NC = (s_order + 1) * (s_order + 2) / 2;
-  const int na = ap_order > 0 ? (ap_order + 1) * (ap_order + 1) : 0;
-  const int nb = bp_order > 0 ? (bp_order + 1) * (bp_order + 1) : 0;
-  const int t = threadIdx.x;
-  if (t >= 8 + na + nb) return;
-  if (t < 2 || (t >= 4 && t < 8)) {
-    // CRVAL_k (t < 2) or CD_kl (t = 4 + kl) through dH/dtheta
-    const int row = t < 2 ? t : 2 + (t - 4);
-    double g = 0.0;
-    for (int i = 0; i < 9; ++i) g += totals[i] * J.dh[row * 9 + i];
-    grad[t] = g;
+// After the backward kernel, in one launch with no block depending on
+// another.  With WCS gradients (nr = ns - 10 blocks): block 0 sums the nine
+// dH and two CRPIX columns and applies the chain rule to CRVAL, CRPIX and CD
+// (dH/dtheta), and writes the AP/BP entries of the square layouts that lie
+// above their order (zero); block 1 + k sums SIP column 11 + k and writes its
+// entry, scaled by S^(p+q) (A.col_entry / A.col_deg; -1: a padded column).
+// The remaining blocks convert rows of the integer sums to grad_src =
+// q 2^-Q.  Grad entries follow dfr_wcs_grad_size: CRVAL(2), CRPIX(2), CD(4),
+// AP, BP.
+__global__ __launch_bounds__(256) void bwd_finish_kernel(FinishArgs A) {
+  __shared__ double sm[11 * 256];
+  __shared__ double tot[11];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if (b >= A.nr) {
+    const double inv = 1.0 / det_scale(A.gmax);
+    const int nc = (int)gridDim.x - A.nr;
+    for (int64_t r = b - A.nr; r < A.h; r += nc) {
+      const unsigned long long *qr = A.q + r * A.w;
+      float *gr = A.gsrc + r * A.gpitch;
+      for (int64_t c = tid; c < A.w; c += 256) gr[c] = (float)((double)(long long)qr[c] * inv);
+    }
     return;
   }
-  if (t < 4) {
-    grad[t] = totals[9 + (t - 2)];  // CRPIX
+  if (b > 0) {
+    const int k = b - 1;
+    column_sum(A, 11 + k, sm);
+    if (tid == 0 && A.col_entry[k] >= 0) {
+      double sc = 1.0;
+      for (int i = 0; i < A.col_deg[k]; ++i) sc *= A.S;
+      A.grad_wcs[A.col_entry[k]] = sm[0] * sc;
+    }
     return;
   }
-  const int poly = t - 8 < na ? 0 : 1;
-  const int o = poly == 0 ? ap_order : bp_order;
-  const int idx = t - 8 - (poly == 0 ? 0 : na);
-  const int p = idx / (o + 1), q = idx % (o + 1);
-  double v = 0.0;
-  if (p + q <= o) {
-    double sc = 1.0;
-    for (int i = 0; i < p + q; ++i) sc *= S;
-    v = totals[11 + poly * NC + tri_n(s_order, p, q)] * sc;
+  // the 11 leading columns in one pass over the rows (each row's are
+  // contiguous), then 11 trees side by side
+  double a[11];
+#pragma unroll
+  for (int c = 0; c < 11; ++c) a[c] = 0.0;
+  for (int k = tid; k < A.n_blocks; k += 256) {
+    const double *row = A.partials + (int64_t)k * A.ns;
+#pragma unroll
+    for (int c = 0; c < 11; ++c) a[c] += row[c];
   }
-  grad[t] = v;
+#pragma unroll
+  for (int c = 0; c < 11; ++c) sm[c * 256 + tid] = a[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+#pragma unroll
+      for (int c = 0; c < 11; ++c) sm[c * 256 + tid] += sm[c * 256 + tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid < 11) tot[tid] = sm[tid * 256];
+  __syncthreads();
+  if (tid < 8) {
+    if (tid < 2 || tid >= 4) {
+      // CRVAL_k (tid < 2) or CD_kl (tid = 4 + kl) through dH/dtheta
+      const int row = tid < 2 ? tid : 2 + (tid - 4);
+      double g = 0.0;
+      for (int i = 0; i < 9; ++i) g += tot[i] * A.J.dh[row * 9 + i];
+      A.grad_wcs[tid] = g;
+    } else {
+      A.grad_wcs[tid] = tot[9 + (tid - 2)];  // CRPIX
+    }
+  }
+  for (int t = tid; t < A.n_above; t += 256) A.grad_wcs[A.above[t]] = 0.0;
 }
 
-hipError_t launch_backward_finish(const double *partials, int n_blocks, int n_sums,
-                                  double *totals, const WcsJacobian &jac, int s_order,
-                                  int ap_order, int bp_order, double s_scale, double *grad_wcs,
-                                  hipStream_t stream) {
-  hipLaunchKernelGGL(bwd_reduce, dim3(n_sums), dim3(256), 0, stream, partials, n_blocks, n_sums,
-                     totals);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !grad_wcs) return e;
-  hipLaunchKernelGGL(bwd_chain, dim3(1), dim3(128), 0, stream, totals, jac, s_order, ap_order,
-                     bp_order, s_scale, grad_wcs);
+hipError_t launch_backward_finish(const FinishArgs &A, hipStream_t stream) {
+  const int nc = A.q ? (int)std::min<int64_t>(2048, A.h) : 0;
+  if (A.nr + nc == 0) return hipSuccess;
+  hipLaunchKernelGGL(bwd_finish_kernel, dim3(A.nr + nc), dim3(256), 0, stream, A);
   return hipGetLastError();
 }
 

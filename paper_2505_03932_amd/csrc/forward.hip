@@ -294,25 +294,6 @@ hipError_t launch_forward_f64(const FramePlan &P, const TrigPlan &T, const TileG
 
 // ------------------------------------------------------------ small kernels
 
-__global__ void zero_f32_kernel(float *p, int64_t rows, int64_t cols, int64_t pitch) {
-  const int64_t n = rows * cols;
-  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  if (pitch == cols && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
-    // contiguous and 16-byte aligned: 16-byte stores, then the tail
-    typedef float f4v __attribute__((ext_vector_type(4)));
-    const int64_t n4 = n >> 2;
-    f4v *q = reinterpret_cast<f4v *>(p);
-    for (int64_t i = t0; i < n4; i += stride) q[i] = (f4v){0.0f, 0.0f, 0.0f, 0.0f};
-    for (int64_t i = (n4 << 2) + t0; i < n; i += stride) p[i] = 0.0f;
-    return;
-  }
-  for (int64_t i = t0; i < n; i += stride) {
-    int64_t r = i / cols;
-    p[r * pitch + (i - r * cols)] = 0.0f;
-  }
-}
-
 __global__ void zero_i32_kernel(int *p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -320,17 +301,6 @@ __global__ void zero_i32_kernel(int *p, int64_t n) {
 }
 
 const void *zero_i32_kernel_ptr() { return reinterpret_cast<const void *>(zero_i32_kernel); }
-
-hipError_t launch_zero_f32(float *p, int64_t rows, int64_t cols, int64_t pitch,
-                           hipStream_t stream) {
-  int64_t n = rows * cols;
-  if (n <= 0) return hipSuccess;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, rows,
-                     cols, pitch);
-  return hipGetLastError();
-}
 
 hipError_t launch_zero_i32(int *p, int64_t n, hipStream_t stream) {
   if (n <= 0) return hipSuccess;

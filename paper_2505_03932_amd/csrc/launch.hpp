@@ -83,23 +83,39 @@ struct WcsJacobian {
 };
 
 // src_acc non-null: the source adjoint too, as integer sums into src_acc
-// [src_h][src_w] (zeroed by the caller), quantised with the scale from
-// gmax_bits (launch_det_prepare); launch_det_finish then writes grad_src.
+// [src_h][src_w] (zeroed by launch_det_prepare), quantised with the scale
+// from max|g| in gmax_bits; launch_backward_finish then writes grad_src.
 hipError_t launch_backward(const FramePlan &P, const TileGeom &G, int interp, int np,
                            const float *grad_out, double *partials, unsigned long long *src_acc,
                            const int *gmax_bits, hipStream_t stream);
-// max |g| into *gmax_bits (which must start at 0).
-hipError_t launch_det_prepare(const float *grad_out, int64_t n, int *gmax_bits,
-                              hipStream_t stream);
-hipError_t launch_det_finish(const unsigned long long *q, int64_t h, int64_t w,
-                             const int *gmax_bits, float *grad_src, int64_t gpitch,
-                             hipStream_t stream);
-hipError_t launch_backward_finish(const double *partials, int n_blocks, int n_sums,
-                                  double *totals, const WcsJacobian &jac, int s_order,
-                                  int ap_order, int bp_order, double s_scale, double *grad_wcs,
-                                  hipStream_t stream);
-hipError_t launch_zero_f32(float *p, int64_t rows, int64_t cols, int64_t pitch,
-                           hipStream_t stream);
+// Zero q[0 .. nq) and *gmax_next, and fold max |g| into *gmax (which must
+// start at 0).
+hipError_t launch_det_prepare(const float *grad_out, int64_t n, unsigned long long *q, int64_t nq,
+                              int *gmax, int *gmax_next, hipStream_t stream);
+// What follows the backward kernel: the WCS partials reduced and chained
+// into grad_wcs (nr = ns - 10 blocks when grad_wcs is wanted, else 0), and
+// the integer sums q (if non-null) converted into grad_src with the scale
+// from *gmax.
+constexpr int kBwdMaxOrder = 5;  // highest source SIP order the backward takes
+constexpr int kBwdSipCols = (kBwdMaxOrder + 1) * (kBwdMaxOrder + 2);  // AP and BP
+constexpr int kBwdSipEntries = 2 * (kBwdMaxOrder + 1) * (kBwdMaxOrder + 1);
+struct FinishArgs {
+  const double *partials;
+  int n_blocks, ns, nr;
+  WcsJacobian J;
+  double S;
+  double *grad_wcs;
+  int col_entry[kBwdSipCols];   // grad entry of SIP column 11 + k, or -1
+  int col_deg[kBwdSipCols];     // its p + q
+  int above[kBwdSipEntries];    // grad entries above their polynomial's order
+  int n_above;
+  const unsigned long long *q;
+  int64_t h, w;
+  float *gsrc;
+  int64_t gpitch;
+  const int *gmax;
+};
+hipError_t launch_backward_finish(const FinishArgs &args, hipStream_t stream);
 hipError_t launch_zero_i32(int *p, int64_t n, hipStream_t stream);
 hipError_t launch_sq_residual(const float *out, const float *ref, const float *mask, int64_t n,
                               double *partials, int n_blocks, double *loss, float *grad_out,

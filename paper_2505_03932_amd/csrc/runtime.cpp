@@ -297,6 +297,24 @@ dfr_status workspace_buffer(Workspace *w, size_t bytes, void **buf) {
   return DFR_OK;
 }
 
+dfr_status workspace_control(Workspace *w, int **ctl) {
+  *ctl = nullptr;
+  if (!w) return DFR_E_DEVICE;
+  if (!w->ctl) {
+    if (hipMalloc(&w->ctl, 256) != hipSuccess) {
+      w->ctl = nullptr;
+      return DFR_E_NOMEM;
+    }
+    w->ctl_dirty = true;
+  }
+  if (w->ctl_dirty) {
+    if (launch_zero_i32(w->ctl, 64, w->stream) != hipSuccess) return DFR_E_DEVICE;
+    w->ctl_dirty = false;
+  }
+  *ctl = w->ctl;
+  return DFR_OK;
+}
+
 namespace {
 
 void destroy_graphs(Workspace &w) {
@@ -322,6 +340,7 @@ void release_workspaces() {
     (void)hipStreamSynchronize(w.stream);
     destroy_graphs(w);
     if (w.buf) (void)hipFree(w.buf);
+    if (w.ctl) (void)hipFree(w.ctl);
     if (w.host_plans) (void)hipHostFree(w.host_plans);
     if (w.staged) (void)hipEventDestroy(w.staged);
     it = g_ws.erase(it);

@@ -72,6 +72,9 @@ struct Workspace {
   hipEvent_t staged = nullptr;      // recorded after the last batch that read host_plans
   bool staged_pending = false;
   std::vector<BatchGraph> graphs;
+  int *ctl = nullptr;      // backward control words: max|g| bits in two alternating slots
+  int ctl_slot = 0;        // the slot the next backward call uses (zero)
+  bool ctl_dirty = true;   // ctl may be non-zero (new, or a call stopped part-way)
 };
 
 std::mutex &workspace_mutex();
@@ -80,6 +83,12 @@ Workspace *workspace(hipStream_t stream);
 // DFR_E_DEVICE if waiting for the stream's earlier work (before replacing a
 // smaller buffer) fails, DFR_E_NOMEM if the allocation fails.
 dfr_status workspace_buffer(Workspace *w, size_t bytes, void **buf);
+// The workspace's backward control words (allocated on first use): slot
+// ctl_slot is zero when the next kernel on its stream runs (each call's
+// first kernel zeroes the other slot, which the next call uses); a call
+// that stops part-way marks them dirty, and they are zeroed here, by a
+// kernel.
+dfr_status workspace_control(Workspace *w, int **ctl);
 void release_workspaces();
 
 // What a batch run produces besides the default per-frame outputs.
