@@ -480,7 +480,7 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
     double t = 0.0;
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) t += (double)wsum[w][tid];
-    partials[(int64_t)tile * NS + tid] = t;
+    partials[(int64_t)tid * G.n_tiles + tile] = t;  // column-major: one column per sum
   }
 }
 
@@ -542,12 +542,14 @@ __global__ __launch_bounds__(256) void det_prepare_kernel(const float *__restric
   if (i0 == 0) *gmax_next = 0;
   // the image is 16-byte aligned (a 256-byte aligned workspace offset)
   typedef unsigned long long u2v __attribute__((ext_vector_type(2)));
+#pragma unroll 4
   for (int64_t i = i0; i < nq / 2; i += stride) reinterpret_cast<u2v *>(q)[i] = u2v{0ull, 0ull};
   if (i0 == 0 && (nq & 1)) q[nq - 1] = 0ull;
   float m = 0.0f;
   // 16-byte loads where the gradient is aligned, then the tail
   typedef float f4v __attribute__((ext_vector_type(4)));
   const int64_t n4 = (reinterpret_cast<uintptr_t>(g) & 15) == 0 ? n / 4 : 0;
+#pragma unroll 4
   for (int64_t i = i0; i < n4; i += stride) {
     const f4v v = reinterpret_cast<const f4v *>(g)[i];
     m = fmaxf(fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y))), fmaxf(fabsf(v.z), fabsf(v.w)));
@@ -558,7 +560,8 @@ __global__ __launch_bounds__(256) void det_prepare_kernel(const float *__restric
   __syncthreads();
   if (threadIdx.x == 0) {
     m = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
-    if (m > 0.0f) atomicMax(gmax, __float_as_int(m));  // one atomic per block
+    // one atomic per block, few blocks: atomics on one address serialise
+    if (m > 0.0f) atomicMax(gmax, __float_as_int(m));
   }
 }
 
@@ -566,18 +569,20 @@ hipError_t launch_det_prepare(const float *grad_out, int64_t n, unsigned long lo
                               int *gmax, int *gmax_next, hipStream_t stream) {
   const int64_t work = std::max<int64_t>(n / 4, nq / 2);
   hipLaunchKernelGGL(det_prepare_kernel,
-                     dim3((unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (work + 255) / 256))),
+                     dim3((unsigned)std::min<int64_t>(512, std::max<int64_t>(1, (work + 255) / 256))),
                      dim3(256), 0, stream, grad_out, n, q, nq, gmax, gmax_next);
   return hipGetLastError();
 }
 
-// Column c of the [n_blocks][ns] partials, summed by one block in a fixed
-// order (256 strided partial sums, then a tree); the result is in sm[0].
+// Column c of the partials ([ns][n_blocks], column-major), summed by one
+// block in a fixed order (256 strided partial sums, then a tree); the
+// result is in sm[0].
 __device__ __forceinline__ void column_sum(const FinishArgs &A, int c, double *sm) {
   const int tid = threadIdx.x;
   double a = 0.0;
+  const double *col = A.partials + (int64_t)c * A.n_blocks;
 #pragma unroll 4
-  for (int k = tid; k < A.n_blocks; k += 256) a += A.partials[(int64_t)k * A.ns + c];
+  for (int k = tid; k < A.n_blocks; k += 256) a += col[k];
   sm[tid] = a;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -619,15 +624,16 @@ __global__ __launch_bounds__(256) void bwd_finish_kernel(FinishArgs A) {
     }
     return;
   }
-  // the 11 leading columns in one pass over the rows (each row's are
-  // contiguous), then 11 trees side by side
+  // the 11 leading columns side by side (one load of each per row, so
+  // eleven are in flight together), then 11 trees side by side
   double a[11];
 #pragma unroll
   for (int c = 0; c < 11; ++c) a[c] = 0.0;
+  const int64_t nb = A.n_blocks;
+#pragma unroll 2
   for (int k = tid; k < A.n_blocks; k += 256) {
-    const double *row = A.partials + (int64_t)k * A.ns;
 #pragma unroll
-    for (int c = 0; c < 11; ++c) a[c] += row[c];
+    for (int c = 0; c < 11; ++c) a[c] += A.partials[c * nb + k];
   }
 #pragma unroll
   for (int c = 0; c < 11; ++c) sm[c * 256 + tid] = a[c];
