@@ -322,6 +322,24 @@ __device__ __forceinline__ unsigned long long det_quant(float v, double qs) {
   return (unsigned long long)(long long)d;
 }
 
+// The two halves of a lane-swap pair summed: permlane32 (lanes 0-31 get
+// a(i) + a(i + 32), lanes 32-63 get b(i - 32) + b(i)) or permlane16 (rows
+// 0 and 2 of 16 lanes get a's pairs of rows 0+1 and 2+3, rows 1 and 3 get
+// b's).  The empty asm makes the swap's two results opaque: without it
+// this compiler folds r[0] + r[1] into r[0] + r[0].
+template <bool ROWS16>
+__device__ __forceinline__ float swap_sum(float a, float b) {
+  const auto r = ROWS16 ? __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a),
+                                                           __builtin_bit_cast(unsigned, b),
+                                                           false, false)
+                        : __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a),
+                                                           __builtin_bit_cast(unsigned, b),
+                                                           false, false);
+  unsigned r0 = r[0], r1 = r[1];
+  asm volatile("" : "+v"(r0), "+v"(r1));
+  return __builtin_bit_cast(float, r0) + __builtin_bit_cast(float, r1);
+}
+
 // SRC: the source gradient is wanted (its integer sums go to gq,
 // [src_h][src_w] dense; det_finish_kernel converts them); without it the
 // kernel carries no scatter code at all.
@@ -469,11 +487,38 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
         }
     }
   }
-  // per-wave, then per-group sums of the WCS terms (skipped tiles give 0)
+  // per-wave, then per-group sums of the WCS terms (skipped tiles give 0):
+  // a transposing butterfly halves the number of live sums at each lane
+  // exchange (lanes i, i + 32, then rows 0/1 and 2/3 of 16 lanes), so each
+  // row of the wave ends with a quarter of the sums, which DPP shifts
+  // reduce within the row (lane 15 holds the row's total).  Fixed order.
+  {
+    constexpr int NSP = NS <= 16 ? 16 : (NS <= 32 ? 32 : 64);
+    constexpr int H = NSP / 2, Q = NSP / 4;
+    static_assert(NS <= 64, "WCS sums per wave");
+    float x[H];
 #pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    float v = wave_sum_dpp(acc[s]);
-    if ((tid & 63) == 0) wsum[tid >> 6][s] = v;
+    for (int s = 0; s < H; ++s) {
+      // lanes 0-31: sum s over lanes i and i + 32; lanes 32-63: sum s + H
+      x[s] = swap_sum<false>(acc[s], s + H < NS ? acc[s + H] : 0.0f);
+    }
+    float y[Q];
+#pragma unroll
+    for (int s = 0; s < Q; ++s) {
+      // row 0: sum s, row 1: s + Q, row 2: s + H, row 3: s + H + Q
+      float v = swap_sum<true>(x[s], x[s + Q]);
+      v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+      v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+      v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+      y[s] = dpp_add<0x118, 0xf>(v);  // row_shr:8
+    }
+    const int lane = tid & 63, row = lane >> 4;
+    if ((lane & 15) == 15) {
+      const int off = row == 0 ? 0 : (row == 1 ? Q : (row == 2 ? H : H + Q));
+#pragma unroll
+      for (int s = 0; s < Q; ++s)
+        if (s + off < NS) wsum[tid >> 6][s + off] = y[s];
+    }
   }
   __syncthreads();
   if (tid < NS) {
