@@ -316,10 +316,22 @@ __device__ __forceinline__ double det_scale(const int *__restrict__ gmax_bits) {
   return m > 0.0f ? ldexp(1.0, 40 - ilogbf(m)) : 1.0;
 }
 
-__device__ __forceinline__ unsigned long long det_quant(float v, double qs) {
-  double d = rint((double)v * qs);
-  d = fmin(fmax(d, -4611686018427387904.0), 4611686018427387904.0);
-  return (unsigned long long)(long long)d;
+// The same scale as an exponent: 2^Q.
+__device__ __forceinline__ int det_exponent(const int *__restrict__ gmax_bits) {
+  const float m = __int_as_float(*gmax_bits);
+  return m > 0.0f ? 40 - ilogbf(m) : 0;
+}
+
+__device__ __forceinline__ unsigned long long det_quant(float v, int Q) {
+  // v 2^Q is exact in FP32 (a power-of-two scale; a result below 2^-126,
+  // which may lose bits, rounds to 0 either way), so rounding it in FP32
+  // gives the integer nearest the exact product; saturated at +-2^62
+  const float y = rintf(__builtin_amdgcn_fmed3f(ldexpf(v, Q), -0x1p62f, 0x1p62f));
+  // an integer of at most 63 bits, split exactly into 32-bit halves
+  const double d = (double)y;
+  const double hi = floor(d * 0x1p-32);
+  const double lo = fma(hi, -0x1p32, d);
+  return ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
 }
 
 // The two halves of a lane-swap pair summed: permlane32 (lanes 0-31 get
@@ -368,7 +380,7 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
     const int bh = T.empty ? 0 : T.bj1 - T.bj0 + 1;
     const int lp = lds_pitch(bw);  // padded row stride (bank spread)
     constexpr bool want_src = SRC;
-    const double qs = SRC ? det_scale(gmax_bits) : 0.0;
+    const int qs = SRC ? det_exponent(gmax_bits) : 0;
     // LDS: the staged box, then the 64-bit integer accumulation box (8-byte
     // aligned, two floats per entry)
     const int lp_acc = 2 * lp;
