@@ -215,10 +215,15 @@ __device__ __forceinline__ void stage_box(const FramePlan &P, int bi0, int bj0, 
 
 // ---- per-pixel adjoint
 
-template <int INTERP, typename Fetch, typename Scatter>
+// FLAT: the taps come from a staged box through `flat` (index(i, j), then
+// value(idx) and add(idx, v) at idx + l * pitch + k), used where every tap
+// is inside the source: no per-tap test, one address per row.  The same
+// arithmetic in the same order as the general loop, so the same bits.
+template <int INTERP, bool FLAT, typename Fetch, typename Scatter, typename Flat>
 __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float ry, int W, int H,
                                                 float a, float g, const Fetch &fetch,
-                                                const Scatter &scatter, float &gx, float &gy) {
+                                                const Scatter &scatter, const Flat &flat,
+                                                float &gx, float &gy) {
   gx = 0.0f;
   gy = 0.0f;
   if constexpr (INTERP == DFR_NEAREST) {
@@ -240,6 +245,31 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
       keys_weights(s, a, wy);
       keys_dweights(t, a, dx);
       keys_dweights(s, a, dy);
+    }
+    if constexpr (FLAT) {
+      if (W >= NT && H >= NT && (unsigned)i0 <= (unsigned)(W - NT) &&
+          (unsigned)j0 <= (unsigned)(H - NT)) {
+        const int base = flat.index(i0, j0);
+        float S = 0.0f, Sx = 0.0f, Sy = 0.0f;
+#pragma unroll
+        for (int l = 0; l < NT; ++l) {
+          const int rb = base + l * flat.pitch();
+          float row = 0.0f, rowd = 0.0f;
+#pragma unroll
+          for (int k = 0; k < NT; ++k) {
+            const float v = flat.value(rb + k);
+            row = fmaf(wx[k], v, row);
+            rowd = fmaf(dx[k], v, rowd);
+            flat.add(rb + k, g * wx[k] * wy[l]);
+          }
+          S = fmaf(wy[l], row, S);
+          Sx = fmaf(wy[l], rowd, Sx);
+          Sy = fmaf(dy[l], row, Sy);
+        }
+        gx = g * Sx;
+        gy = g * Sy;
+        return true;
+      }
     }
     bool inx[NT], iny[NT];
     bool all_in = true;
@@ -322,6 +352,23 @@ __device__ __forceinline__ int det_exponent(const int *__restrict__ gmax_bits) {
   return m > 0.0f ? 40 - ilogbf(m) : 0;
 }
 
+__device__ __forceinline__ unsigned long long det_quant(float v, int Q);
+
+// A pixel's taps in the staged box and, for the source adjoint, its 64-bit
+// integer accumulation copy (same index, same row stride).
+template <bool SRC>
+struct BwdFlat {
+  const float *vals;
+  unsigned long long *qacc;
+  int lp, bi0, bj0, Q;
+  __device__ int index(int i, int j) const { return (j - bj0) * lp + (i - bi0); }
+  __device__ int pitch() const { return lp; }
+  __device__ float value(int idx) const { return vals[idx]; }
+  __device__ void add(int idx, float v) const {
+    if constexpr (SRC) atomicAdd(&qacc[idx], det_quant(v, Q));
+  }
+};
+
 __device__ __forceinline__ unsigned long long det_quant(float v, int Q) {
   // v 2^Q is exact in FP32 (a power-of-two scale; a result below 2^-126,
   // which may lose bits, rounds to 0 either way), so rounding it in FP32
@@ -356,7 +403,8 @@ __device__ __forceinline__ float swap_sum(float a, float b) {
 // [src_h][src_w] dense; det_finish_kernel converts them); without it the
 // kernel carries no scatter code at all.
 template <int INTERP, int SORD, int NP, bool TSIP, bool SRC>
-__global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom G,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NP == 1 ? 5 : 1)))
+void reproject_bwd(FramePlan P, TileGeom G,
                                                           const float *__restrict__ gout,
                                                           double *__restrict__ partials,
                                                           unsigned long long *__restrict__ gq,
@@ -405,6 +453,7 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
     auto scat_glb = [&](int, int, int i, int j, float v) {
       if (want_src) atomicAdd(&gq[(int64_t)j * W + i], det_quant(v, qs));
     };
+    const BwdFlat<SRC> flat{vals, qacc, lp, bi0, bj0, qs};
     const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
     const float S_s = (float)P.s_scale;
     // Every tap's contribution is quantised and added on its own (64-bit
@@ -429,11 +478,12 @@ __global__ __launch_bounds__(kThreads) void reproject_bwd(FramePlan P, TileGeom 
         float gx, gy;
         bool cov;
         if (use_lds)
-          cov = interp_backward<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs,
-                                        G.cubic_a, g, fetch_lds, scat_lds, gx, gy);
+          cov = interp_backward<INTERP, true>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs,
+                                              G.cubic_a, g, fetch_lds, scat_lds, flat, gx, gy);
         else
-          cov = interp_backward<INTERP>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W, Hs,
-                                        G.cubic_a, g, fetch_glb, scat_glb, gx, gy);
+          cov = interp_backward<INTERP, false>(T.abx[k], T.aby[k], T.rx[k][e], T.ry[k][e], W,
+                                               Hs, G.cubic_a, g, fetch_glb, scat_glb, flat, gx,
+                                               gy);
         if (cov) {
           gxs[e] = gx;
           gys[e] = gy;
