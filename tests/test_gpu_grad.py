@@ -281,3 +281,37 @@ def test_deterministic_full_size_alignment(dfr, orc):
     ogs, ogw, _, oga = orc.grad(c.src, c.src_wcs, c.tgt_wcs, c.out_shape, 2, gn, want_abs=True)
     _compare_wcs_grad(a[1].cpu().numpy(), ogw, oga, rel_tol=1e-4)
     assert np.abs(a[0].cpu().numpy() - ogs).max() <= SRC_TOL * np.abs(gn).max()
+
+
+def test_backward_streams_and_gradient_scales(dfr):
+    """Backward calls on two streams in turn, with gradients of very
+    different magnitudes in turn (so max|g|, kept per stream in two
+    alternating control words, changes from call to call), give the bits a
+    call on the default stream gives for the same gradient."""
+    c, _ = grad_case(300)
+    src = torch.from_numpy(c.src).cuda()
+    rng = np.random.default_rng(22)
+    grads = [torch.from_numpy((rng.normal(0, 1, c.out_shape) * sc).astype(np.float32)).cuda()
+             for sc in (1.0, 1e-6, 3e4)]
+    want = []
+    for g in grads:
+        gs, gw = dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic", g)
+        torch.cuda.synchronize()
+        want.append((gs.clone(), gw.clone()))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(3):
+        for k, g in enumerate(grads):
+            st = streams[(rep + k) % 2]
+            st.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(st):
+                gs, gw = dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic",
+                                                g)
+            st.synchronize()
+            assert torch.equal(gs, want[k][0]), (rep, k)
+            assert torch.equal(gw, want[k][1]), (rep, k)
+    # an argument error leaves the next call's result unchanged
+    with pytest.raises(Exception):
+        dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, (-1, 5), "bicubic", grads[0])
+    gs, gw = dfr.reproject_backward(src, c.src_wcs, c.tgt_wcs, c.out_shape, "bicubic", grads[2])
+    torch.cuda.synchronize()
+    assert torch.equal(gs, want[2][0]) and torch.equal(gw, want[2][1])
