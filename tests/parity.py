@@ -7,7 +7,8 @@ Criteria (FP32 path against the FP64 oracle):
              oracle's FP64 interpolation at the GPU's own position and
              C = sum|w v| / F the magnitude of the terms being combined (the
              scale a relative FP32 error of a weighted sum refers to);
-  footprint  |F_gpu - F_oracle(pos_gpu)| <= 2e-6 (FP32 sums of <= 4 weights);
+  footprint  |F_gpu - F_oracle(pos_gpu)| <= 1e-6 (FP32 sums of <= 4 weights per axis
+             and their product: a few ulp of 1; measured <= 3.5e-7);
   coverage   covered on one side and not the other only where the oracle's
              footprint at the GPU position is below 1e-6 (a decision of F > 0
              within rounding of zero);
@@ -20,7 +21,7 @@ import numpy as np
 
 POS_TOL = 1e-3
 REL_TOL = 1e-5
-FP_TOL = 2e-6
+FP_TOL = 1e-6
 F_EDGE = 1e-6
 
 
