@@ -128,7 +128,9 @@ int choose_tile(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, in
   // heuristic: the measured default for the kernel and interpolation unless
   // the map turns its source box much larger per output pixel than the
   // 64x32 tile's (a rotated map and a flat tile); then 64x32 when its box
-  // fits the LDS budget, else the largest tile whose box does
+  // fits the LDS budget (or the square 64x64 tile when its box is smaller
+  // per output pixel still: 218 against 225 us on the 8192^2 frame rotated
+  // by 45 degrees), else the largest tile whose box does
   {
     if (pref < 1 || pref > kTileCount) pref = forward_default_tile(interp);
     TileShape a, b;
@@ -140,8 +142,18 @@ int choose_tile(const FramePlan &P, int32_t out_h, int32_t out_w, int interp, in
         na / (a.width * a.height) <= 1.5 * nb / (b.width * b.height))
       return pref;
   }
-  if (lds_factor * lds_need(P, out_h, out_w, interp, kDefaultTile) <= kLdsMaxFloats)
+  const double nb = lds_need(P, out_h, out_w, interp, kDefaultTile);
+  if (lds_factor * nb <= kLdsMaxFloats) {
+    constexpr int kSquareTile = 6;  // 64 x 64, four rows per thread
+    TileShape b, c;
+    tile_shape(kDefaultTile, b);
+    tile_shape(kSquareTile, c);
+    const double nc = lds_need(P, out_h, out_w, interp, kSquareTile);
+    if (lds_factor * nc <= kLdsMaxFloats &&
+        nc / (c.width * c.height) <= 0.95 * nb / (b.width * b.height))
+      return kSquareTile;
     return kDefaultTile;
+  }
   const int order[] = {4, 8, 1, 7, 10};
   for (int t : order)
     if (lds_factor * lds_need(P, out_h, out_w, interp, t) <= kLdsMaxFloats) return t;
