@@ -201,6 +201,7 @@ def test_target_sip_has_no_model(dfr):
     a, b = draw_sip(2, 128.0, np.random.default_rng(1))
     m = dfr.cell_model(c.src_wcs, c.tgt_wcs.copy(a=a, b=b), 3, 4)
     assert not m["certified"] and m["bound"] >= 1e29
+    assert m["tie"] == 0.5  # no model: every nearest decision would be taken in FP64
 
 
 def test_coarse_far_field_is_uncertified_but_bounded(dfr, orc):
