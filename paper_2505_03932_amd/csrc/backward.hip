@@ -229,7 +229,7 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
   if constexpr (INTERP == DFR_NEAREST) {
     int i = bx + (int)rintf(rx), j = by + (int)rintf(ry);
     bool in = ((unsigned)i < (unsigned)W) && ((unsigned)j < (unsigned)H);
-    if (in) scatter(0, 0, i, j, g);
+    if (in) scatter(0, 0, i, j, flat.scaled(g));
     return in;
   } else {
     constexpr int NT = INTERP == DFR_BILINEAR ? 2 : 4;
@@ -250,6 +250,10 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
       if (W >= NT && H >= NT && (unsigned)i0 <= (unsigned)(W - NT) &&
           (unsigned)j0 <= (unsigned)(H - NT)) {
         const int base = flat.index(i0, j0);
+        const float gs = flat.scaled(g);
+        float gw[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) gw[k] = gs * wx[k];
         float S = 0.0f, Sx = 0.0f, Sy = 0.0f;
 #pragma unroll
         for (int l = 0; l < NT; ++l) {
@@ -260,7 +264,7 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
             const float v = flat.value(rb + k);
             row = fmaf(wx[k], v, row);
             rowd = fmaf(dx[k], v, rowd);
-            flat.add(rb + k, g * wx[k] * wy[l]);
+            flat.add_scaled(rb + k, gw[k] * wy[l]);
           }
           S = fmaf(wy[l], row, S);
           Sx = fmaf(wy[l], rowd, Sx);
@@ -292,6 +296,7 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
     if (!(F > 0.0f)) return false;
     float iF = all_in ? 1.0f : __builtin_amdgcn_rcpf(F);
     float c = g * iF;
+    const float cs = flat.scaled(c);  // the source adjoint's contributions, times 2^Q
     // Where taps leave the source, d out = (dS - out dF) / F cancels the
     // level of the values; taking every value relative to one in-bounds tap
     // (exact: the in-bounds taps form a product set, so both dS and out dF
@@ -317,7 +322,7 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
           float v = fetch(i0 + k, j0 + l) - vr;
           row = fmaf(wx[k], v, row);
           rowd = fmaf(dx[k], v, rowd);
-          scatter(k, l, i0 + k, j0 + l, c * wx[k] * wy[l]);
+          scatter(k, l, i0 + k, j0 + l, cs * wx[k] * wy[l]);
         }
       }
       S = fmaf(wy[l], row, S);
@@ -352,10 +357,27 @@ __device__ __forceinline__ int det_exponent(const int *__restrict__ gmax_bits) {
   return m > 0.0f ? 40 - ilogbf(m) : 0;
 }
 
-__device__ __forceinline__ unsigned long long det_quant(float v, int Q);
+// An FP32 integer of at most 63 bits as a 64-bit integer, split exactly
+// into 32-bit halves.
+__device__ __forceinline__ unsigned long long det_int(float y) {
+  const double d = (double)y;
+  const double hi = floor(d * 0x1p-32);
+  const double lo = fma(hi, -0x1p32, d);
+  return ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
+}
+
+// A contribution already scaled by 2^Q (formed as (g/F 2^Q) wx wy: the
+// scaling of g/F is exact), rounded to the nearest integer in FP32 and
+// saturated at +-2^62.
+__device__ __forceinline__ unsigned long long det_quant(float y) {
+  return det_int(rintf(__builtin_amdgcn_fmed3f(y, -0x1p62f, 0x1p62f)));
+}
 
 // A pixel's taps in the staged box and, for the source adjoint, its 64-bit
-// integer accumulation copy (same index, same row stride).
+// integer accumulation copy (same index, same row stride).  On this path
+// every tap is inside the source (F = 1): |g| 2^Q < 2^41 and |wx wy| <= 1,
+// so the contributions need no saturation; they are formed exactly as on
+// the general path, so a pixel gives the same integers on either.
 template <bool SRC>
 struct BwdFlat {
   const float *vals;
@@ -364,22 +386,12 @@ struct BwdFlat {
   __device__ int index(int i, int j) const { return (j - bj0) * lp + (i - bi0); }
   __device__ int pitch() const { return lp; }
   __device__ float value(int idx) const { return vals[idx]; }
-  __device__ void add(int idx, float v) const {
-    if constexpr (SRC) atomicAdd(&qacc[idx], det_quant(v, Q));
+  __device__ float scaled(float g) const { return ldexpf(g, Q); }
+  // y = (g 2^Q wx) wy
+  __device__ void add_scaled(int idx, float y) const {
+    if constexpr (SRC) atomicAdd(&qacc[idx], det_int(rintf(y)));
   }
 };
-
-__device__ __forceinline__ unsigned long long det_quant(float v, int Q) {
-  // v 2^Q is exact in FP32 (a power-of-two scale; a result below 2^-126,
-  // which may lose bits, rounds to 0 either way), so rounding it in FP32
-  // gives the integer nearest the exact product; saturated at +-2^62
-  const float y = rintf(__builtin_amdgcn_fmed3f(ldexpf(v, Q), -0x1p62f, 0x1p62f));
-  // an integer of at most 63 bits, split exactly into 32-bit halves
-  const double d = (double)y;
-  const double hi = floor(d * 0x1p-32);
-  const double lo = fma(hi, -0x1p32, d);
-  return ((unsigned long long)(unsigned)(int)hi << 32) | (unsigned long long)(unsigned)lo;
-}
 
 // The two halves of a lane-swap pair summed: permlane32 (lanes 0-31 get
 // a(i) + a(i + 32), lanes 32-63 get b(i - 32) + b(i)) or permlane16 (rows
@@ -448,10 +460,10 @@ void reproject_bwd(FramePlan P, TileGeom G,
     auto fetch_lds = [&](int i, int j) -> float { return vals[(j - bj0) * lp + (i - bi0)]; };
     auto fetch_glb = [&](int i, int j) -> float { return P.src[(int64_t)j * P.pitch + i]; };
     auto scat_lds = [&](int, int, int i, int j, float v) {
-      if (want_src) atomicAdd(&qacc[(j - bj0) * lp + (i - bi0)], det_quant(v, qs));
+      if (want_src) atomicAdd(&qacc[(j - bj0) * lp + (i - bi0)], det_quant(v));
     };
     auto scat_glb = [&](int, int, int i, int j, float v) {
-      if (want_src) atomicAdd(&gq[(int64_t)j * W + i], det_quant(v, qs));
+      if (want_src) atomicAdd(&gq[(int64_t)j * W + i], det_quant(v));
     };
     const BwdFlat<SRC> flat{vals, qacc, lp, bi0, bj0, qs};
     const float tinv = (float)P.t_inv_scale, sinv = (float)P.s_inv_scale;
