@@ -103,13 +103,11 @@ typedef struct dfr_options {
   double *debug_positions;
   /* dfr_reproject_backward: request a grad_src that is bitwise reproducible
    * across runs and tile shapes.  Both 0 and 1 give that result: the source
-   * adjoint is always summed exactly.  Every contribution g w / F (or a
-   * thread's FP32 sum of its own run of four output pixels' contributions
-   * to one source pixel, a grouping fixed by the output grid) is rounded to
-   * a multiple of 2^-Q, 2^-Q = 2^-40 max|g| rounded down to a power of two,
-   * and the multiples are summed in 64-bit integers, so no order or
-   * grouping of the additions matters; |g w / F| beyond 2^22 max|g|
-   * saturates.  The WCS gradient is reduced in a fixed order for a given
+   * adjoint is always summed exactly.  Every contribution g w / F is
+   * rounded to a multiple of 2^-Q, 2^-Q = 2^-30 max|g| rounded down to a
+   * power of two (a rounding of at most 2^-31 max|g| per contribution), and
+   * the multiples are summed in 64-bit integers, so no order or grouping of
+   * the additions matters; |g w / F| beyond 2^32 max|g| saturates.  The WCS gradient is reduced in a fixed order for a given
    * tile shape. */
   int32_t deterministic;
   int32_t reserved_;      /* must be 0 */

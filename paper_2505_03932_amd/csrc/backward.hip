@@ -338,23 +338,27 @@ __device__ __forceinline__ bool interp_backward(int bx, int by, float rx, float 
 }
 
 // Source adjoint: every contribution v = g w / F is rounded to a
-// multiple of 2^-Q (Q fixed per call from max |g|: 2^-Q = 2^-40 max |g|,
+// multiple of 2^-Q (Q fixed per call from max |g|: 2^-Q = 2^-30 max |g|,
 // rounded to a power of two) and the multiples are summed in 64-bit
 // integers.  Integer sums do not depend on the order or the grouping of
 // the additions, so the result is the same bits for every run and every
 // tile shape; 64-bit LDS integer adds are also much faster here than
 // ds_add_f32 on contended addresses (measured: 148 against 382 us per
-// 2048^2 bicubic backward with one add per tap).  |v| beyond 2^22 max |g|
-// (footprints below ~2.4e-7 at frame edges) saturates at +-2^62.
+// 2048^2 bicubic backward with one add per tap).  The rounding (at most
+// 2^-31 max |g| per contribution) stays far below an FP32 sum's; where
+// every tap is inside the source |v| 2^Q < 2^31, one 32-bit conversion;
+// |v| beyond 2^32 max |g| (footprints below ~2.3e-10 at frame edges)
+// saturates at +-2^62.
+constexpr int kDetBits = 30;
 __device__ __forceinline__ double det_scale(const int *__restrict__ gmax_bits) {
   const float m = __int_as_float(*gmax_bits);
-  return m > 0.0f ? ldexp(1.0, 40 - ilogbf(m)) : 1.0;
+  return m > 0.0f ? ldexp(1.0, kDetBits - ilogbf(m)) : 1.0;
 }
 
 // The same scale as an exponent: 2^Q.
 __device__ __forceinline__ int det_exponent(const int *__restrict__ gmax_bits) {
   const float m = __int_as_float(*gmax_bits);
-  return m > 0.0f ? 40 - ilogbf(m) : 0;
+  return m > 0.0f ? kDetBits - ilogbf(m) : 0;
 }
 
 // An FP32 integer of at most 63 bits as a 64-bit integer, split exactly
@@ -375,9 +379,11 @@ __device__ __forceinline__ unsigned long long det_quant(float y) {
 
 // A pixel's taps in the staged box and, for the source adjoint, its 64-bit
 // integer accumulation copy (same index, same row stride).  On this path
-// every tap is inside the source (F = 1): |g| 2^Q < 2^41 and |wx wy| <= 1,
-// so the contributions need no saturation; they are formed exactly as on
-// the general path, so a pixel gives the same integers on either.
+// every tap is inside the source (F = 1): |g| 2^Q < 2^31 and |wx wy| <= 1,
+// and each rounded product is at most |g| 2^Q, so a contribution is an
+// integer below 2^31 in magnitude: one 32-bit conversion, no saturation.
+// The contributions are formed exactly as on the general path, so a pixel
+// gives the same integers on either.
 template <bool SRC>
 struct BwdFlat {
   const float *vals;
@@ -389,7 +395,8 @@ struct BwdFlat {
   __device__ float scaled(float g) const { return ldexpf(g, Q); }
   // y = (g 2^Q wx) wy
   __device__ void add_scaled(int idx, float y) const {
-    if constexpr (SRC) atomicAdd(&qacc[idx], det_int(rintf(y)));
+    if constexpr (SRC)
+      atomicAdd(&qacc[idx], (unsigned long long)(long long)(int)rintf(y));
   }
 };
 
