@@ -419,7 +419,7 @@ __device__ __forceinline__ float swap_sum(float a, float b) {
 }
 
 // SRC: the source gradient is wanted (its integer sums go to gq,
-// [src_h][src_w] dense; det_finish_kernel converts them); without it the
+// [src_h][src_w] dense; bwd_finish_kernel converts them); without it the
 // kernel carries no scatter code at all.
 template <int INTERP, int SORD, int NP, bool TSIP, bool SRC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NP == 1 ? 5 : 1)))
